@@ -99,6 +99,8 @@ def lib():
         L.or_pair_updates.restype = ctypes.c_uint64
         L.or_reset_pair_updates.argtypes = []
         L.or_reset_pair_updates.restype = None
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -266,3 +268,8 @@ def pair_updates() -> int:
 
 def reset_pair_updates() -> None:
     lib().or_reset_pair_updates()
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().or_num_threads())

@@ -412,3 +412,11 @@ int or_finite_diff_grad(int n, uint64_t x0, const or_gate* gates, int n_gates,
     free(s); free(work);
     return 0;
 }
+
+/* Threads the OpenMP loops use (the CPU-baseline reports it). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif

@@ -1,0 +1,908 @@
+// C ABI of the state-vector engine: handles, argument checks, gate-table
+// upload, pass execution, FP64 reductions and the adjoint sweep.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sv.h"
+#include "gates.h"
+#include "qv_internal.h"
+
+using namespace qv;
+
+namespace {
+
+thread_local std::string g_err;
+
+sv_status fail(sv_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(SV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+struct TimingRec {
+    int kind;
+    hipEvent_t e0, e1;
+};
+
+}  // namespace
+
+struct sv_state_t {
+    int n = 0;
+    sv_dtype dtype = SV_C128;
+    size_t elem = 16;
+    void* buf = nullptr;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // gate tables: pinned host staging + device copy
+    unsigned char* h_table = nullptr;
+    size_t h_table_cap = 0;
+    void* d_table = nullptr;
+    size_t d_table_cap = 0;
+    hipEvent_t table_done = nullptr;
+    bool table_pending = false;
+
+    // reduction scratch
+    double* d_part = nullptr;
+    size_t d_part_cap = 0;  // doubles
+    double* d_res = nullptr;
+    size_t d_res_cap = 0;   // doubles
+    double* h_res = nullptr;
+    size_t h_res_cap = 0;   // doubles (pinned)
+
+    // timing
+    bool timing = false;
+    std::vector<TimingRec> recs;
+    std::vector<hipEvent_t> pool;
+    double acc_ms[KF_COUNT] = {};
+    int64_t acc_n[KF_COUNT] = {};
+};
+
+namespace {
+
+// Keeps the caller's current device and restores it on exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+sv_status ensure_device(void** p, size_t* cap, size_t bytes, hipStream_t st)
+{
+    if (*cap >= bytes) return SV_OK;
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(st));  // older launches may still read it
+        HIP_TRY(hipFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t want = bytes < 4096 ? 4096 : bytes + bytes / 2;
+    if (hipMalloc(p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(SV_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    *cap = want;
+    return SV_OK;
+}
+
+sv_status ensure_part(sv_state s, size_t doubles)
+{
+    size_t cap = s->d_part_cap * sizeof(double);
+    void* p = s->d_part;
+    sv_status st = ensure_device(&p, &cap, doubles * sizeof(double), s->stream);
+    s->d_part = (double*)p;
+    s->d_part_cap = cap / sizeof(double);
+    return st;
+}
+
+sv_status ensure_res(sv_state s, size_t doubles)
+{
+    size_t cap = s->d_res_cap * sizeof(double);
+    void* p = s->d_res;
+    sv_status st = ensure_device(&p, &cap, doubles * sizeof(double), s->stream);
+    s->d_res = (double*)p;
+    s->d_res_cap = cap / sizeof(double);
+    if (st != SV_OK) return st;
+    if (s->h_res_cap < doubles) {
+        if (s->h_res) {
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            HIP_TRY(hipHostFree(s->h_res));
+            s->h_res = nullptr;
+            s->h_res_cap = 0;
+        }
+        const size_t want = doubles < 512 ? 512 : doubles + doubles / 2;
+        if (hipHostMalloc((void**)&s->h_res, want * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->h_res = nullptr;
+            return fail(SV_ENOMEM, "pinned host allocation failed");
+        }
+        s->h_res_cap = want;
+    }
+    return SV_OK;
+}
+
+// ----------------------------------------------------------- timing ---
+
+hipEvent_t take_event(sv_state s)
+{
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct LaunchTimer {
+    sv_state s;
+    int kind;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LaunchTimer(sv_state s_, int kind_) : s(s_), kind(kind_)
+    {
+        if (s->timing) {
+            e0 = take_event(s);
+            e1 = take_event(s);
+            if (e0) (void)hipEventRecord(e0, s->stream);
+        }
+    }
+    ~LaunchTimer()
+    {
+        if (s->timing && e0 && e1) {
+            (void)hipEventRecord(e1, s->stream);
+            s->recs.push_back({kind, e0, e1});
+        }
+    }
+};
+
+sv_status drain_timing(sv_state s)
+{
+    if (s->recs.empty()) return SV_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (auto& r : s->recs) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
+        s->acc_ms[r.kind] += ms;
+        s->acc_n[r.kind] += 1;
+        s->pool.push_back(r.e0);
+        s->pool.push_back(r.e1);
+    }
+    s->recs.clear();
+    return SV_OK;
+}
+
+// --------------------------------------------------------- validation ---
+
+sv_status check_state(sv_state s)
+{
+    if (!s) return fail(SV_EINVAL, "null state handle");
+    return SV_OK;
+}
+
+sv_status build_gates(sv_state s, const sv_gate* gates, int n_gates, std::vector<HostGate>* out)
+{
+    if (n_gates < 0) return fail(SV_EINVAL, "n_gates < 0");
+    if (n_gates > 0 && !gates) return fail(SV_EINVAL, "null gate array");
+    out->clear();
+    out->reserve(n_gates);
+    for (int i = 0; i < n_gates; i++) {
+        const std::string why = check_gate(gates[i], s->n);
+        if (!why.empty()) return fail(SV_EINVAL, "gate " + std::to_string(i) + ": " + why);
+        std::string uns;
+        if (unsupported_gate(gates[i], &uns)) return fail(SV_EUNSUPPORTED, "gate " + std::to_string(i) + ": " + uns);
+        out->push_back(build_gate(gates[i]));
+    }
+    return SV_OK;
+}
+
+sv_status check_terms(sv_state s, const sv_pauli* terms, int n_terms)
+{
+    if (n_terms < 0) return fail(SV_EINVAL, "n_terms < 0");
+    if (n_terms > 0 && !terms) return fail(SV_EINVAL, "null term array");
+    const uint64_t all = (1ull << s->n) - 1;
+    for (int t = 0; t < n_terms; t++) {
+        if ((terms[t].x_mask | terms[t].z_mask) & ~all)
+            return fail(SV_EINVAL, "term " + std::to_string(t) + " acts on a qubit >= n");
+        if (!std::isfinite(terms[t].coeff)) return fail(SV_EINVAL, "non-finite coefficient");
+    }
+    return SV_OK;
+}
+
+// Terms grouped by x mask (first-appearance order), at most kTermsPerLaunch
+// per batch; coefficients carry i^{#Y}.
+std::vector<TermBatch> batch_terms(const sv_pauli* terms, int n_terms)
+{
+    std::vector<TermBatch> out;
+    std::map<uint64_t, std::vector<int>> by_x;
+    std::vector<uint64_t> order;
+    for (int t = 0; t < n_terms; t++) {
+        auto it = by_x.find(terms[t].x_mask);
+        if (it == by_x.end()) {
+            order.push_back(terms[t].x_mask);
+            by_x[terms[t].x_mask].push_back(t);
+        } else {
+            it->second.push_back(t);
+        }
+    }
+    for (uint64_t x : order) {
+        const std::vector<int>& idx = by_x[x];
+        for (size_t k = 0; k < idx.size(); k += kTermsPerLaunch) {
+            TermBatch tb{};
+            tb.x_mask = x;
+            for (size_t j = k; j < idx.size() && j < k + kTermsPerLaunch; j++) {
+                const sv_pauli& p = terms[idx[j]];
+                const int ny = __builtin_popcountll(p.x_mask & p.z_mask) & 3;
+                static const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+                tb.z_mask[tb.n_terms] = p.z_mask;
+                tb.coeff_re[tb.n_terms] = p.coeff * re[ny];
+                tb.coeff_im[tb.n_terms] = p.coeff * im[ny];
+                tb.n_terms++;
+            }
+            out.push_back(tb);
+        }
+    }
+    return out;
+}
+
+// ------------------------------------------------------ plan execution ---
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <typename T>
+sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, std::vector<size_t>* hdr_off,
+                        size_t* ops_off, size_t* mats_off)
+{
+    size_t n_hdr = 0, n_ops = 0, n_mats = 0;
+    for (const auto& p : passes)
+        if (p.kind == PlanPass::BLOCK) {
+            n_hdr++;
+            n_ops += p.ops.size();
+            n_mats += p.mats.size();
+        }
+    hdr_off->clear();
+    if (n_hdr == 0) return SV_OK;
+    const size_t b_hdr = n_hdr * sizeof(PassHdr);
+    *ops_off = align_up(b_hdr, 256);
+    *mats_off = align_up(*ops_off + n_ops * sizeof(TileOp), 256);
+    const size_t total = *mats_off + n_mats * sizeof(T);
+
+    if (s->table_pending) {  // the staging buffer may still feed the last copy
+        HIP_TRY(hipEventSynchronize(s->table_done));
+        s->table_pending = false;
+    }
+    if (s->h_table_cap < total) {
+        if (s->h_table) HIP_TRY(hipHostFree(s->h_table));
+        s->h_table = nullptr;
+        const size_t want = total + total / 2 + 4096;
+        if (hipHostMalloc((void**)&s->h_table, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->h_table_cap = 0;
+            return fail(SV_ENOMEM, "pinned host allocation failed");
+        }
+        s->h_table_cap = want;
+    }
+    sv_status st = ensure_device(&s->d_table, &s->d_table_cap, total, s->stream);
+    if (st != SV_OK) return st;
+
+    PassHdr* H = reinterpret_cast<PassHdr*>(s->h_table);
+    TileOp* O = reinterpret_cast<TileOp*>(s->h_table + *ops_off);
+    T* M = reinterpret_cast<T*>(s->h_table + *mats_off);
+    size_t ih = 0, io = 0, im = 0;
+    for (const auto& p : passes) {
+        if (p.kind != PlanPass::BLOCK) continue;
+        PassHdr h = p.hdr;
+        h.op_begin = (int32_t)io;
+        H[ih] = h;
+        hdr_off->push_back(ih * sizeof(PassHdr));
+        ih++;
+        for (const TileOp& op : p.ops) {
+            TileOp t = op;
+            t.mat += (int32_t)im;
+            O[io++] = t;
+        }
+        for (const cd& v : p.mats) {
+            using R = std::remove_reference_t<decltype(M[0].x)>;
+            T e;
+            e.x = (R)v.real();
+            e.y = (R)v.imag();
+            M[im++] = e;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(s->d_table, s->h_table, total, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipEventRecord(s->table_done, s->stream));
+    s->table_pending = true;
+    return SV_OK;
+}
+
+// Run a plan on one state (s1 == nullptr) or on phi and lambda (adjoint);
+// grad rows of each block pass are summed into d_gvals + running offset.
+template <typename T>
+sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1, int n_states,
+                   std::vector<int>* grad_rows_per_pass, double* d_gvals)
+{
+    std::vector<size_t> hdr_off;
+    size_t ops_off = 0, mats_off = 0;
+    sv_status st = upload_tables<T>(s, passes, &hdr_off, &ops_off, &mats_off);
+    if (st != SV_OK) return st;
+    const unsigned char* base = reinterpret_cast<const unsigned char*>(s->d_table);
+    const PassHdr* d_hdr = reinterpret_cast<const PassHdr*>(base);
+    const TileOp* d_ops = reinterpret_cast<const TileOp*>(base + ops_off);
+    const T* d_mats = reinterpret_cast<const T*>(base + mats_off);
+
+    size_t ih = 0;
+    int64_t gval_off = 0;
+    for (size_t p = 0; p < passes.size(); p++) {
+        const PlanPass& pp = passes[p];
+        if (pp.kind == PlanPass::BLOCK) {
+            const int b = pp.hdr.b;
+            const int64_t nblocks = (int64_t)1 << (s->n - b);
+            const int rows = grad_rows_per_pass ? (*grad_rows_per_pass)[p] : 0;
+            if (rows > 0) {
+                st = ensure_part(s, (size_t)rows * nblocks);
+                if (st != SV_OK) return st;
+            }
+            {
+                LaunchTimer tm(s, n_states == 2 ? KF_ADJ_BLOCK : KF_BLOCK);
+                HIP_TRY((launch_block_pass<T>(s0, s1, s->n, n_states, d_hdr + hdr_off[ih] / sizeof(PassHdr), d_ops,
+                                              d_mats, b, s->d_part, nblocks, s->stream)));
+            }
+            ih++;
+            if (rows > 0) {
+                LaunchTimer tm(s, KF_REDUCE);
+                HIP_TRY(launch_sum_rows(s->d_part, rows, nblocks, nblocks, d_gvals + gval_off, s->stream));
+                gval_off += rows;
+            }
+        } else {
+            for (int k = 0; k < n_states; k++) {
+                T* tgt = k == 0 ? s0 : s1;
+                if (pp.kind == PlanPass::SWEEP1) {
+                    LaunchTimer tm(s, KF_SWEEP1);
+                    HIP_TRY(launch_sweep1<T>(tgt, s->n, pp.gate, s->stream));
+                } else if (pp.kind == PlanPass::SWEEP2) {
+                    LaunchTimer tm(s, KF_SWEEP2);
+                    HIP_TRY(launch_sweep2<T>(tgt, s->n, pp.gate, s->stream));
+                } else {
+                    LaunchTimer tm(s, KF_DIAG);
+                    HIP_TRY(launch_sweep_diag<T>(tgt, s->n, pp.gate, s->stream));
+                }
+            }
+        }
+    }
+    return SV_OK;
+}
+
+template <typename F>
+sv_status dispatch(sv_state s, F&& f)
+{
+    if (s->dtype == SV_C128) return f(static_cast<d2*>(s->buf));
+    return f(static_cast<f2*>(s->buf));
+}
+
+PlanOptions plan_options(int n, size_t elem, int n_states)
+{
+    PlanOptions o;
+    o.n_states = n_states;
+    o.b = default_block_qubits(n, (int)elem, n_states);
+    // keep 128-byte runs contiguous in memory: 8 complex128 / 16 complex64
+    o.coalesce = elem == 16 ? 3 : 4;
+    return o;
+}
+
+std::vector<PlanItem> forward_items(const std::vector<HostGate>& hg)
+{
+    std::vector<PlanItem> items(hg.size());
+    for (size_t i = 0; i < hg.size(); i++) items[i].g = hg[i];
+    return items;
+}
+
+// Sum rows of per-block partials into d_res[0..rows), copy to h_res, wait.
+sv_status finish_rows(sv_state s, int rows, int64_t count)
+{
+    sv_status st = ensure_res(s, rows);
+    if (st != SV_OK) return st;
+    {
+        LaunchTimer tm(s, KF_REDUCE);
+        HIP_TRY(launch_sum_rows(s->d_part, rows, count, count, s->d_res, s->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(s->h_res, s->d_res, rows * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+template <typename T>
+sv_status expect_impl(sv_state s, T* psi, const std::vector<TermBatch>& batches, double* out)
+{
+    const int np = kReduceBlocks;
+    if (batches.empty()) {
+        *out = 0;
+        return SV_OK;
+    }
+    sv_status st = ensure_part(s, batches.size() * (size_t)np);
+    if (st != SV_OK) return st;
+    for (size_t k = 0; k < batches.size(); k++) {
+        LaunchTimer tm(s, KF_REDUCE);
+        HIP_TRY(launch_pauli_expect<T>(psi, s->n, batches[k], s->d_part + k * np, np, s->stream));
+    }
+    st = finish_rows(s, (int)batches.size(), np);
+    if (st != SV_OK) return st;
+    double f = 0;
+    for (size_t k = 0; k < batches.size(); k++) f += s->h_res[k];
+    *out = f;
+    return SV_OK;
+}
+
+template <typename T>
+sv_status pauli_apply_impl(sv_state s, const T* psi, T* dst, const std::vector<TermBatch>& batches)
+{
+    if (batches.empty()) {
+        TermBatch zero{};
+        LaunchTimer tm(s, KF_REDUCE);
+        HIP_TRY(launch_pauli_apply<T>(psi, dst, s->n, zero, false, s->stream));
+        return SV_OK;
+    }
+    for (size_t k = 0; k < batches.size(); k++) {
+        LaunchTimer tm(s, KF_REDUCE);
+        HIP_TRY(launch_pauli_apply<T>(psi, dst, s->n, batches[k], k > 0, s->stream));
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI ===
+
+extern "C" {
+
+const char* sv_last_error(void) { return g_err.c_str(); }
+
+sv_status sv_alloc(sv_state* out, int n_qubits, sv_dtype dtype, void* device_buf, size_t buf_bytes,
+                   void* hip_stream)
+{
+    g_err.clear();
+    if (!out) return fail(SV_EINVAL, "null output handle");
+    *out = nullptr;
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) return fail(SV_EINVAL, "n_qubits must be in [1, 34]");
+    const size_t elem = dtype == SV_C128 ? 16 : 8;
+    const size_t need = ((size_t)1 << n_qubits) * elem;
+    if (device_buf) {
+        if (buf_bytes < need)
+            return fail(SV_EINVAL, "buffer of " + std::to_string(buf_bytes) + " bytes < 2^n * " +
+                                       std::to_string(elem) + " = " + std::to_string(need));
+        if (reinterpret_cast<uintptr_t>(device_buf) % 16) return fail(SV_EINVAL, "buffer not 16-byte aligned");
+    }
+    sv_state s = new (std::nothrow) sv_state_t;
+    if (!s) return fail(SV_ENOMEM, "host allocation failed");
+    s->n = n_qubits;
+    s->dtype = dtype;
+    s->elem = elem;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(SV_EDEVICE, "no HIP device");
+    }
+    if (device_buf) {
+        s->buf = device_buf;
+    } else {
+        if (hipMalloc(&s->buf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(SV_ENOMEM, "device allocation of the state failed");
+        }
+        s->owns = true;
+    }
+    if (hipEventCreateWithFlags(&s->table_done, hipEventDisableTiming) != hipSuccess) {
+        if (s->owns) (void)hipFree(s->buf);
+        delete s;
+        return fail(SV_EDEVICE, "event creation failed");
+    }
+    *out = s;
+    return SV_OK;
+}
+
+sv_status sv_free(sv_state s)
+{
+    g_err.clear();
+    if (!s) return SV_OK;
+    DeviceGuard dg(s->device);
+    sv_status st = SV_OK;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) st = fail(SV_EDEVICE, "stream failed before free");
+    for (auto& r : s->recs) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    for (auto e : s->pool) (void)hipEventDestroy(e);
+    if (s->table_done) (void)hipEventDestroy(s->table_done);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->h_table) (void)hipHostFree(s->h_table);
+    if (s->d_part) (void)hipFree(s->d_part);
+    if (s->d_res) (void)hipFree(s->d_res);
+    if (s->h_res) (void)hipHostFree(s->h_res);
+    if (s->owns && s->buf) (void)hipFree(s->buf);
+    delete s;
+    return st;
+}
+
+void* sv_data(sv_state s) { return s ? s->buf : nullptr; }
+int sv_num_qubits(sv_state s) { return s ? s->n : 0; }
+sv_dtype sv_get_dtype(sv_state s) { return s ? s->dtype : SV_C128; }
+
+sv_status sv_set_basis(sv_state s, uint64_t x)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (x >> s->n) return fail(SV_EINVAL, "basis index >= 2^n");
+    DeviceGuard dg(s->device);
+    LaunchTimer tm(s, KF_INIT);
+    return dispatch(s, [&](auto* psi) -> sv_status {
+        HIP_TRY(launch_init_basis(psi, s->n, x, s->stream));
+        return SV_OK;
+    });
+}
+
+sv_status sv_apply_gate(sv_state s, int n_targets, const int* targets, int n_controls, const int* controls,
+                        const double* matrix)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (n_targets != 1 && n_targets != 2) return fail(SV_EINVAL, "n_targets must be 1 or 2");
+    if (!targets || !matrix) return fail(SV_EINVAL, "null targets or matrix");
+    if (n_controls < 0 || n_controls > 2) return fail(SV_EINVAL, "n_controls must be 0..2");
+    if (n_controls > 0 && !controls) return fail(SV_EINVAL, "null controls");
+    sv_gate g{};
+    g.op = n_targets == 1 ? SV_OP_MATRIX1 : SV_OP_MATRIX2;
+    g.qubits[0] = targets[0];
+    g.qubits[1] = n_targets == 2 ? targets[1] : 0;
+    g.n_controls = n_controls;
+    for (int c = 0; c < n_controls; c++) g.controls[c] = controls[c];
+    g.param_index = -1;
+    std::memcpy(g.matrix, matrix, sizeof(double) * (n_targets == 1 ? 8 : 32));
+    return sv_apply_unfused(s, &g, 1);
+}
+
+sv_status sv_apply_unfused(sv_state s, const sv_gate* gates, int n_gates)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    std::vector<HostGate> hg;
+    sv_status st = build_gates(s, gates, n_gates, &hg);
+    if (st != SV_OK) return st;
+    DeviceGuard dg(s->device);
+    return dispatch(s, [&](auto* psi) -> sv_status {
+        using T = std::remove_pointer_t<decltype(psi)>;
+        for (const HostGate& g : hg) {
+            if (g.kind == G_DENSE1) {
+                LaunchTimer tm(s, KF_SWEEP1);
+                HIP_TRY(launch_sweep1<T>(psi, s->n, g, s->stream));
+            } else if (g.kind == G_DENSE2) {
+                LaunchTimer tm(s, KF_SWEEP2);
+                HIP_TRY(launch_sweep2<T>(psi, s->n, g, s->stream));
+            } else {
+                LaunchTimer tm(s, KF_DIAG);
+                HIP_TRY(launch_sweep_diag<T>(psi, s->n, sweep_form(g), s->stream));
+            }
+        }
+        return SV_OK;
+    });
+}
+
+sv_status sv_apply_fused(sv_state s, const sv_gate* gates, int n_gates)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    std::vector<HostGate> hg;
+    sv_status st = build_gates(s, gates, n_gates, &hg);
+    if (st != SV_OK) return st;
+    if (hg.empty()) return SV_OK;
+    DeviceGuard dg(s->device);
+    std::vector<PlanPass> passes;
+    try {
+        passes = plan_circuit(s->n, forward_items(hg), plan_options(s->n, s->elem, 1), (int)s->elem);
+    } catch (const std::exception& e) {
+        return fail(SV_EINVAL, std::string("planner: ") + e.what());
+    }
+    return dispatch(s, [&](auto* psi) -> sv_status {
+        using T = std::remove_pointer_t<decltype(psi)>;
+        return run_plan<T>(s, passes, psi, nullptr, 1, nullptr, nullptr);
+    });
+}
+
+sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gates, sv_plan_stats* out)
+{
+    g_err.clear();
+    if (!out) return fail(SV_EINVAL, "null output");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) return fail(SV_EINVAL, "n_qubits must be in [1, 34]");
+    sv_state_t tmp;
+    tmp.n = n_qubits;
+    tmp.dtype = dtype;
+    tmp.elem = dtype == SV_C128 ? 16 : 8;
+    std::vector<HostGate> hg;
+    sv_status st = build_gates(&tmp, gates, n_gates, &hg);
+    if (st != SV_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->n_gates = n_gates;
+    const PlanOptions o = plan_options(n_qubits, tmp.elem, 1);
+    out->block_qubits = std::min(o.b, n_qubits);
+    if (hg.empty()) return SV_OK;
+    try {
+        const auto passes = plan_circuit(n_qubits, forward_items(hg), o, (int)tmp.elem);
+        for (const auto& p : passes) {
+            out->n_passes++;
+            if (p.kind == PlanPass::BLOCK) out->n_block_passes++;
+            out->bytes_moved += p.bytes;
+        }
+    } catch (const std::exception& e) {
+        return fail(SV_EINVAL, std::string("planner: ") + e.what());
+    }
+    return SV_OK;
+}
+
+sv_status sv_norm2(sv_state s, double* out)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (!out) return fail(SV_EINVAL, "null output");
+    DeviceGuard dg(s->device);
+    sv_pauli one{1.0, 0, 0};
+    const auto batches = batch_terms(&one, 1);
+    return dispatch(s, [&](auto* psi) { return expect_impl(s, psi, batches, out); });
+}
+
+sv_status sv_expect(sv_state s, const sv_pauli* terms, int n_terms, double* out)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (!out) return fail(SV_EINVAL, "null output");
+    sv_status st = check_terms(s, terms, n_terms);
+    if (st != SV_OK) return st;
+    DeviceGuard dg(s->device);
+    const auto batches = batch_terms(terms, n_terms);
+    return dispatch(s, [&](auto* psi) { return expect_impl(s, psi, batches, out); });
+}
+
+sv_status sv_apply_pauli_sum(sv_state s, const sv_pauli* terms, int n_terms, void* dst_buf, size_t dst_bytes)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    sv_status st = check_terms(s, terms, n_terms);
+    if (st != SV_OK) return st;
+    const size_t need = ((size_t)1 << s->n) * s->elem;
+    if (!dst_buf || dst_bytes < need) return fail(SV_EINVAL, "destination buffer missing or too small");
+    if (reinterpret_cast<uintptr_t>(dst_buf) % 16) return fail(SV_EINVAL, "destination not 16-byte aligned");
+    const char* a = static_cast<const char*>(s->buf);
+    const char* d = static_cast<const char*>(dst_buf);
+    if (d < a + need && a < d + need) return fail(SV_EINVAL, "destination overlaps the state");
+    DeviceGuard dg(s->device);
+    const auto batches = batch_terms(terms, n_terms);
+    return dispatch(s, [&](auto* psi) -> sv_status {
+        using T = std::remove_pointer_t<decltype(psi)>;
+        return pauli_apply_impl<T>(s, psi, static_cast<T*>(dst_buf), batches);
+    });
+}
+
+sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const sv_pauli* terms, int n_terms,
+                          void* work_buf, size_t work_bytes, double* grad_out, int n_params, double* expval_out)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (n_params < 0) return fail(SV_EINVAL, "n_params < 0");
+    if (n_params > 0 && !grad_out) return fail(SV_EINVAL, "null grad_out");
+    sv_status st = check_terms(s, terms, n_terms);
+    if (st != SV_OK) return st;
+    const size_t need = ((size_t)1 << s->n) * s->elem;
+    if (!work_buf || work_bytes < need) return fail(SV_EINVAL, "work buffer missing or too small");
+    if (reinterpret_cast<uintptr_t>(work_buf) % 16) return fail(SV_EINVAL, "work buffer not 16-byte aligned");
+    {
+        const char* a = static_cast<const char*>(s->buf);
+        const char* d = static_cast<const char*>(work_buf);
+        if (d < a + need && a < d + need) return fail(SV_EINVAL, "work buffer overlaps the state");
+    }
+    std::vector<HostGate> hg;
+    st = build_gates(s, gates, n_gates, &hg);
+    if (st != SV_OK) return st;
+    for (int i = 0; i < n_gates; i++)
+        if (hg[i].param >= n_params)
+            return fail(SV_EINVAL, "gate " + std::to_string(i) + ": param_index >= n_params");
+    DeviceGuard dg(s->device);
+
+    // Reverse sweep items: gradient read, then the inverse gate. A grad item's
+    // slot is its position among the grad items (reverse gate order).
+    std::vector<PlanItem> items;
+    std::vector<int> slot_gate;  // grad slot -> gate index
+    items.reserve(hg.size());
+    for (int l = n_gates - 1; l >= 0; l--) {
+        PlanItem it;
+        it.g = dagger(hg[l]);
+        it.g.gen = hg[l].gen;
+        if (hg[l].param >= 0) {
+            it.grad = true;
+            it.grad_slot = (int32_t)slot_gate.size();
+            slot_gate.push_back(l);
+        }
+        items.push_back(it);
+    }
+    std::vector<PlanPass> passes;
+    try {
+        PlanOptions o = plan_options(s->n, s->elem, 2);
+        o.single_gate_sweeps = false;
+        passes = plan_circuit(s->n, items, o, (int)s->elem);
+    } catch (const std::exception& e) {
+        return fail(SV_EINVAL, std::string("planner: ") + e.what());
+    }
+    // Renumber the grad reads pass by pass: the rows of one pass are
+    // contiguous in the device result array, in op order.
+    std::vector<int> rows_per_pass(passes.size(), 0);
+    std::vector<int> row_gate;  // result row -> gate index
+    for (size_t p = 0; p < passes.size(); p++) {
+        int local = 0;
+        for (TileOp& op : passes[p].ops)
+            if (op.kind == T_GRAD) {
+                row_gate.push_back(slot_gate[op.slot]);
+                op.slot = local++;
+            }
+        rows_per_pass[p] = local;
+    }
+    const int n_grad = (int)row_gate.size();
+
+    return dispatch(s, [&](auto* psi) -> sv_status {
+        using T = std::remove_pointer_t<decltype(psi)>;
+        T* lam = static_cast<T*>(work_buf);
+        const auto batches = batch_terms(terms, n_terms);
+        sv_status st2 = pauli_apply_impl<T>(s, psi, lam, batches);
+        if (st2 != SV_OK) return st2;
+        // f = Re <psi|H psi>
+        const int np = kReduceBlocks;
+        st2 = ensure_part(s, 2 * (size_t)np);
+        if (st2 != SV_OK) return st2;
+        {
+            LaunchTimer tm(s, KF_REDUCE);
+            HIP_TRY(launch_inner<T>(psi, lam, s->n, s->d_part, np, s->stream));
+        }
+        st2 = finish_rows(s, 2, np);
+        if (st2 != SV_OK) return st2;
+        const double f = s->h_res[0];
+        st2 = ensure_res(s, (size_t)(n_grad > 0 ? n_grad : 1));
+        if (st2 != SV_OK) return st2;
+        st2 = run_plan<T>(s, passes, psi, lam, 2, &rows_per_pass, s->d_res);
+        if (st2 != SV_OK) return st2;
+        if (n_grad > 0)
+            HIP_TRY(hipMemcpyAsync(s->h_res, s->d_res, n_grad * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        std::vector<double> per_gate(hg.size(), 0.0);
+        for (int r = 0; r < n_grad; r++) per_gate[row_gate[r]] = s->h_res[r];
+        for (int p = 0; p < n_params; p++) grad_out[p] = 0;
+        for (size_t l = 0; l < hg.size(); l++)
+            if (hg[l].param >= 0) grad_out[hg[l].param] += per_gate[l];
+        if (expval_out) *expval_out = f;
+        return SV_OK;
+    });
+}
+
+sv_status sv_compare(sv_state a, sv_state b, sv_diff* out)
+{
+    g_err.clear();
+    if (!a || !b) return fail(SV_EINVAL, "null state handle");
+    if (!out) return fail(SV_EINVAL, "null output");
+    if (a->n != b->n) return fail(SV_EINVAL, "qubit counts differ");
+    if (a->device != b->device) return fail(SV_EINVAL, "states on different devices");
+    DeviceGuard dg(a->device);
+    const int np = kReduceBlocks;
+    HIP_TRY(hipStreamSynchronize(b->stream));  // b's pending work lands before a's stream reads it
+    sv_status st = ensure_part(a, 6 * (size_t)np);
+    if (st != SV_OK) return st;
+    st = ensure_res(a, 6);
+    if (st != SV_OK) return st;
+    {
+        LaunchTimer tm(a, KF_REDUCE);
+        hipError_t e;
+        if (a->dtype == SV_C128 && b->dtype == SV_C128)
+            e = launch_compare<d2, d2>((const d2*)a->buf, (const d2*)b->buf, a->n, a->d_part, np, a->stream);
+        else if (a->dtype == SV_C128)
+            e = launch_compare<d2, f2>((const d2*)a->buf, (const f2*)b->buf, a->n, a->d_part, np, a->stream);
+        else if (b->dtype == SV_C128)
+            e = launch_compare<f2, d2>((const f2*)a->buf, (const d2*)b->buf, a->n, a->d_part, np, a->stream);
+        else
+            e = launch_compare<f2, f2>((const f2*)a->buf, (const f2*)b->buf, a->n, a->d_part, np, a->stream);
+        HIP_TRY(e);
+        HIP_TRY(launch_compare_finish(a->d_part, np, a->d_res, a->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(a->h_res, a->d_res, 6 * sizeof(double), hipMemcpyDeviceToHost, a->stream));
+    HIP_TRY(hipStreamSynchronize(a->stream));
+    out->max_abs = a->h_res[0];
+    out->l2 = std::sqrt(a->h_res[1]);
+    out->inner_re = a->h_res[2];
+    out->inner_im = a->h_res[3];
+    out->norm2_a = a->h_res[4];
+    out->norm2_b = a->h_res[5];
+    return SV_OK;
+}
+
+sv_status sv_copy(sv_state s, void* dst, const void* src, size_t bytes)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (!dst || !src) return fail(SV_EINVAL, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | bytes) % 16)
+        return fail(SV_EINVAL, "pointers and size must be multiples of 16 bytes");
+    const char* a = static_cast<const char*>(src);
+    const char* d = static_cast<const char*>(dst);
+    if (bytes && d < a + bytes && a < d + bytes) return fail(SV_EINVAL, "ranges overlap");
+    if (!bytes) return SV_OK;
+    DeviceGuard dg(s->device);
+    LaunchTimer tm(s, KF_COPY);
+    HIP_TRY(launch_copy(dst, src, bytes, s->stream));
+    return SV_OK;
+}
+
+sv_status sv_sync(sv_state s)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    DeviceGuard dg(s->device);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+sv_status sv_timing_enable(sv_state s, int on)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    s->timing = on != 0;
+    return SV_OK;
+}
+
+sv_status sv_timing_reset(sv_state s)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    DeviceGuard dg(s->device);
+    sv_status st = drain_timing(s);
+    for (int k = 0; k < KF_COUNT; k++) {
+        s->acc_ms[k] = 0;
+        s->acc_n[k] = 0;
+    }
+    return st;
+}
+
+sv_status sv_timing_read(sv_state s, int kernel, int64_t* launches, double* total_ms)
+{
+    g_err.clear();
+    if (check_state(s)) return SV_EINVAL;
+    if (kernel < 0 || kernel >= KF_COUNT) return fail(SV_EINVAL, "kernel family out of range");
+    if (!launches || !total_ms) return fail(SV_EINVAL, "null output");
+    DeviceGuard dg(s->device);
+    sv_status st = drain_timing(s);
+    if (st != SV_OK) return st;
+    *launches = s->acc_n[kernel];
+    *total_ms = s->acc_ms[kernel];
+    return SV_OK;
+}
+
+}  // extern "C"

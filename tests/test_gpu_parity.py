@@ -1,0 +1,345 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: max-abs amplitude 1e-12 for complex128 and 1e-5 for complex64
+(the precision targets of the engine); expectations and gradients as stated
+per test. Sizes span n <= b (one block), n = b + 1 (two blocks), several
+blocks, and every target qubit including 0, b - 1, b and n - 1."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import circuits as C
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+DTYPES = [torch.complex128, torch.complex64]
+
+
+@pytest.fixture(scope="module")
+def qv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_15545_amd as qv
+    return qv
+
+
+def load(qv, n, psi, dtype):
+    st = qv.State(n, dtype)
+    st.tensor.copy_(torch.from_numpy(psi).to(dtype))
+    return st
+
+
+def host(st):
+    torch.cuda.synchronize()
+    return st.tensor.to(torch.complex128).cpu().numpy()
+
+
+def maxabs(a, b):
+    return float(np.max(np.abs(a - b)))
+
+
+# ------------------------------------------------------------ single gates ---
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 5, 12, 13, 15])
+def test_every_op_every_qubit_unfused_and_fused(qv, n, dtype):
+    print(f"single gates n={n} dtype={dtype}", flush=True)
+    rng = C.rng_for(100 + n)
+    psi = C.random_state(n, n)
+    qs = sorted({0, n - 1, min(11, n - 1), min(12, n - 1), n // 2})
+    gates = []
+    for q in qs:
+        for op in ("h", "x", "y", "z", "s", "t", "sdg", "tdg"):
+            gates.append(C.gate(op, q))
+        gates.append(C.gate("rx", q, params=(0.3,)))
+        gates.append(C.gate("ry", q, params=(1.3,)))
+        gates.append(C.gate("rz", q, params=(2.3,)))
+        gates.append(C.gate("p", q, params=(0.9,)))
+        gates.append(C.gate("u3", q, params=tuple(rng.uniform(0, 2 * math.pi, 3))))
+        gates.append(C.gate("mat1", q, params=C.matrix_params(C.random_unitary(2, rng))))
+    if n >= 2:
+        for a in qs:
+            for b in qs:
+                if a == b:
+                    continue
+                gates.append(C.gate("cx", a, b))
+                gates.append(C.gate("cz", a, b))
+                gates.append(C.gate("cp", a, b, params=(0.77,)))
+                gates.append(C.gate("swap", a, b))
+                gates.append(C.gate("mat2", a, b, params=C.matrix_params(C.random_unitary(4, rng))))
+    want = psi.copy()
+    for g in gates:
+        want = oracle.apply_gate(want, n, g)
+    for fused in (False, True):
+        st = load(qv, n, psi, dtype)
+        st.apply(gates, fused=fused)
+        err = maxabs(host(st), want)
+        assert err <= TOL[dtype], (fused, err)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_apply_matrix_with_controls(qv, dtype):
+    n = 14
+    rng = C.rng_for(5)
+    psi = C.random_state(n, 5)
+    st = load(qv, n, psi, dtype)
+    want = psi.copy()
+    for (t, ctrls) in [(0, (13,)), (13, (0, 7)), (12, (3,)), (5, (12, 13))]:
+        u = C.random_unitary(2, rng)
+        st.apply_matrix([t], u, controls=ctrls)
+        mask = sum(1 << c for c in ctrls)
+        want = oracle.apply_1q(want, n, t, u, ctrl_mask=mask)
+    for (a, b) in [(0, 13), (12, 2)]:
+        u4 = C.random_unitary(4, rng)
+        st.apply_matrix([a, b], u4)
+        want = oracle.apply_2q(want, n, a, b, u4)
+    assert maxabs(host(st), want) <= TOL[dtype]
+
+
+# ------------------------------------------------------------ circuits ---
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,n_gates,seed", [(3, 60, 0), (11, 200, 1), (12, 200, 2), (13, 300, 3),
+                                            (16, 400, 4), (19, 300, 5)])
+def test_random_mixed_circuits(qv, n, n_gates, seed, dtype):
+    print(f"mixed n={n} gates={n_gates} seed={seed} dtype={dtype}", flush=True)
+    circ = C.random_mixed_circuit(n, n_gates, seed)
+    want = oracle.run(circ, n)
+    for fused in (True, False):
+        st = qv.State(n, dtype).set_basis(0).apply(circ, fused=fused)
+        err = maxabs(host(st), want)
+        assert err <= TOL[dtype], (fused, err)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_config_16q_random_u3_cnot_depth20(qv, seed):
+    """16 qubits, complex128, depth 20 of U3 on every qubit + CNOT matching."""
+    n = 16
+    circ = C.random_u3_layers(n, 20, seed)
+    want = oracle.run(circ, n)
+    st = qv.State(n, torch.complex128).set_basis(0).apply(circ)
+    assert maxabs(host(st), want) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_random_circuit_22q_against_oracle(qv, dtype):
+    n = 22
+    circ = C.random_u3_layers(n, 6, 7, entangler="cz")
+    want = oracle.run(circ, n)
+    st = qv.State(n, dtype).set_basis(0).apply(circ)
+    assert maxabs(host(st), want) <= TOL[dtype]
+
+
+# ------------------------------------------------------------ closed forms ---
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 13, 20])
+def test_uniform_state(qv, n, dtype):
+    st = qv.State(n, dtype).set_basis(0).apply([C.gate("h", q) for q in range(n)])
+    got = host(st)
+    assert np.max(np.abs(got - 2 ** (-n / 2))) <= TOL[dtype] * 2 ** (-n / 2) * 10
+
+
+def qft_closed_form(n, x, ys):
+    N = 1 << n
+    ph = np.array([(x * int(y)) % N for y in ys], dtype=np.float64) / N
+    return np.exp(2j * np.pi * ph) / math.sqrt(N)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,seed", [(4, 0), (12, 1), (17, 2), (21, 3)])
+def test_qft_closed_form(qv, n, seed, dtype):
+    x = C.random_basis_index(n, seed)
+    st = qv.State(n, dtype).set_basis(x).apply(C.qft(n))
+    got = host(st)
+    assert maxabs(got, qft_closed_form(n, x, range(1 << n))) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("n", [3, 16, 24])
+def test_ghz(qv, n):
+    circ = [C.gate("h", 0)] + [C.gate("cx", 0, q) for q in range(1, n)]
+    st = qv.State(n, torch.complex128).set_basis(0).apply(circ)
+    got = host(st)
+    want = np.zeros(1 << n, dtype=np.complex128)
+    want[0] = want[-1] = 2 ** -0.5
+    assert maxabs(got, want) <= 1e-15
+
+
+def test_set_basis_and_norm(qv):
+    for n, x in [(1, 1), (9, 300), (20, 12345)]:
+        st = qv.State(n, torch.complex128).set_basis(x)
+        got = host(st)
+        want = np.zeros(1 << n)
+        want[x] = 1
+        assert np.array_equal(got, want)
+        assert st.norm2() == 1.0
+
+
+# ------------------------------------------------------------ expectations ---
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,seed", [(1, 0), (6, 1), (14, 2)])
+def test_expectation_random_pauli_sums(qv, n, seed, dtype):
+    psi = C.random_state(n, seed)
+    terms = C.random_pauli_sum(n, 40, seed) + [(0.25, 0, 0), (-0.5, 1, 1), (0.7, 0, 1 << (n - 1))]
+    st = load(qv, n, psi, dtype)
+    psi_in = host(st)  # the stored (possibly rounded) state
+    want = oracle.expect(psi_in, n, terms)
+    got = st.expect(terms)
+    assert abs(got - want) <= (1e-12 if dtype == torch.complex128 else 1e-12 * len(terms))
+    assert abs(st.norm2() - oracle.expect(psi_in, n, [(1.0, 0, 0)])) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [5, 14])
+def test_apply_pauli_sum(qv, n, dtype):
+    psi = C.random_state(n, 3)
+    terms = C.random_pauli_sum(n, 25, 3)
+    st = load(qv, n, psi, dtype)
+    psi_in = host(st)
+    out = st.apply_pauli_sum(terms)
+    torch.cuda.synchronize()
+    got = out.to(torch.complex128).cpu().numpy()
+    assert maxabs(got, oracle.apply_pauli_sum(psi_in, n, terms)) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+def test_expectation_hea_observable_closed_forms(qv):
+    n = 20
+    H = C.zz_x_chain(n)
+    st = qv.State(n, torch.complex128).set_basis(0)
+    assert abs(st.expect(H) - (n - 1)) <= 1e-12
+    st.apply([C.gate("h", q) for q in range(n)])
+    assert abs(st.expect(H) - 0.5 * n) <= 1e-12
+
+
+# ------------------------------------------------------------ gradients ---
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,layers", [(3, 2), (8, 3), (13, 2)])
+def test_adjoint_matches_oracle(qv, n, layers, dtype):
+    print(f"adjoint n={n} layers={layers} dtype={dtype}", flush=True)
+    th = C.hea_params(n, layers, seed=n)
+    circ = C.hea(n, layers, th)
+    H = C.zz_x_chain(n)
+    P = 2 * n * layers
+    f_o, g_o = oracle.adjoint_grad(circ, n, H, P)
+    st = qv.State(n, dtype).set_basis(0).apply(circ)
+    f, g = st.adjoint_grad(circ, H, P)
+    tol = 1e-10 if dtype == torch.complex128 else 1e-4
+    assert abs(f - f_o) <= tol
+    assert np.max(np.abs(g - g_o)) <= tol
+    # the state was walked back to e_0 by the inverse gates
+    back = host(st)
+    e0 = np.zeros(1 << n)
+    e0[0] = 1
+    assert maxabs(back, e0) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+def test_adjoint_rx_and_shared_parameters(qv):
+    n = 6
+    circ = [C.gate("h", q) for q in range(n)]
+    circ += [C.gate("rx", 1, params=(0.4,), param_index=0), C.gate("cx", 0, 2),
+             C.gate("rx", 2, params=(0.4,), param_index=0), C.gate("ry", 5, params=(1.1,), param_index=1),
+             C.gate("rz", 0, params=(-0.6,), param_index=2), C.gate("cx", 5, 1),
+             C.gate("rz", 4, params=(0.2,), param_index=1)]
+    terms = C.random_pauli_sum(n, 10, 9)
+    f_o, g_o = oracle.adjoint_grad(circ, n, terms, 3)
+    st = qv.State(n, torch.complex128).set_basis(0).apply(circ)
+    f, g = st.adjoint_grad(circ, terms, 3)
+    assert abs(f - f_o) <= 1e-12
+    np.testing.assert_allclose(g, g_o, atol=1e-12)
+
+
+def test_config_20q_hea_adjoint_vs_oracle_fd_and_shift(qv):
+    """20 qubits, 10 layers, 400 parameters; complex128."""
+    n, layers = 20, 10
+    P = 2 * n * layers
+    th = C.hea_params(n, layers, seed=0)
+    circ = C.hea(n, layers, th)
+    H = C.zz_x_chain(n)
+    st = qv.State(n, torch.complex128).set_basis(0).apply(circ)
+    f, g = st.adjoint_grad(circ, H, P)
+    f_o, g_o = oracle.adjoint_grad(circ, n, H, P)
+    assert abs(f - f_o) <= 1e-10
+    assert np.max(np.abs(g - g_o)) <= 1e-10
+
+    def value(thetas):
+        s = qv.State(n, torch.complex128).set_basis(0).apply(C.with_params(circ, thetas))
+        return s.expect(H)
+
+    sub = C.rng_for(1).choice(P, size=32, replace=False)
+    for p in sub:
+        e = np.zeros(P)
+        e[p] = 1.0
+        fd = (value(th + 1e-6 * e) - value(th - 1e-6 * e)) / 2e-6
+        ps = 0.5 * (value(th + 0.5 * math.pi * e) - value(th - 0.5 * math.pi * e))
+        assert abs(fd - g[p]) <= 1e-7, (p, fd, g[p])
+        assert abs(ps - g[p]) <= 1e-10, (p, ps, g[p])
+
+
+def test_autograd_function(qv):
+    n, layers = 6, 2
+    th = torch.tensor(C.hea_params(n, layers, seed=4), dtype=torch.float64, requires_grad=True)
+    circ = C.hea(n, layers, th.detach().numpy())
+    H = C.zz_x_chain(n)
+    f = qv.expectation(th, circ, H, n, torch.complex128)
+    f.backward()
+    f_o, g_o = oracle.adjoint_grad(circ, n, H, th.numel())
+    assert abs(f.item() - f_o) <= 1e-12
+    np.testing.assert_allclose(th.grad.numpy(), g_o, atol=1e-12)
+
+
+# ------------------------------------------------------------ device utils ---
+
+def test_compare_c64_against_c128(qv):
+    n = 18
+    circ = C.random_u3_layers(n, 8, 3, entangler="cz")
+    a = qv.State(n, torch.complex128).set_basis(0).apply(circ)
+    b = qv.State(n, torch.complex64).set_basis(0).apply(circ)
+    d = a.compare(b)
+    ha, hb = host(a), host(b)
+    assert abs(d["max_abs"] - np.max(np.abs(ha - hb))) <= 1e-15
+    assert abs(d["l2"] - np.linalg.norm(ha - hb)) <= 1e-12
+    inner = np.vdot(ha, hb)
+    assert abs(d["inner_re"] - inner.real) <= 1e-12 and abs(d["inner_im"] - inner.imag) <= 1e-12
+    assert abs(d["norm2_a"] - 1) <= 1e-12 and abs(d["norm2_b"] - 1) <= 1e-5
+    assert d["max_abs"] <= 1e-5
+
+
+def test_copy_kernel(qv):
+    n = 20
+    st = qv.State(n, torch.complex128)
+    src = torch.randn(1 << n, dtype=torch.complex128, device="cuda")
+    dst = torch.empty_like(src)
+    qv.copy(st, dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+
+
+def test_bad_arguments_leave_state_untouched(qv):
+    n = 8
+    st = qv.State(n, torch.complex128).set_basis(3)
+    before = host(st)
+    with pytest.raises(qv.SvError):
+        st.apply([C.gate("h", 0), C.gate("h", 9)])
+    with pytest.raises(qv.SvError):
+        st.set_basis(1 << n)
+    with pytest.raises(qv.SvError):
+        st.expect([(1.0, 1 << n, 0)])
+    assert np.array_equal(host(st), before)
+
+
+def test_timing_counts_launches(qv):
+    n = 16
+    st = qv.State(n, torch.complex128)
+    st.timing(True)
+    st.timing_reset()
+    st.set_basis(0).apply(C.random_u3_layers(n, 3, 0))
+    from paper_2508_15545_amd import _binding as B
+    launches, ms = st.timing_read(B.KF_BLOCK)
+    assert launches >= 1 and ms > 0
+    assert st.timing_read(B.KF_INIT)[0] == 1
