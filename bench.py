@@ -82,6 +82,26 @@ def cpu_baseline(n: int, rand, seconds_budget: float = 20.0):
     }
 
 
+def copy_probe(qv, B, n, dtype, elem, reps):
+    """Read + write bandwidth of the library's copy kernel at the state size."""
+    torch.cuda.set_device(0)
+    st = qv.State(n, dtype, device="cuda:0")
+    src = st.tensor
+    src.zero_()
+    dst = torch.empty_like(src)
+    qv.copy(st, dst, src)
+    st.timing(True)
+    st.timing_reset()
+    for _ in range(reps):
+        qv.copy(st, dst, src)
+    launches, ms = st.timing_read(B.KF_COPY)
+    nbytes = (1 << n) * elem
+    gbs = 2.0 * nbytes * launches / (ms / 1e3) / 1e9
+    print(json.dumps({"copy_probe": {"bytes_per_launch_read": nbytes, "bytes_per_launch_write": nbytes,
+                                     "launches": launches, "avg_ms": ms / launches, "gbs": gbs}}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +111,8 @@ def main() -> int:
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time the library's streaming copy kernel on two state-sized buffers")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,6 +126,8 @@ def main() -> int:
     n = args.n
     dtype = torch.complex128 if args.dtype == "c128" else torch.complex64
     elem = 16 if args.dtype == "c128" else 8
+    if args.copy_probe:
+        return copy_probe(qv, B, n, dtype, elem, args.steps)
     rand, x, qft = workload(n)
     gates_per_step = len(rand) + len(qft)
     plan_r = qv.plan_stats(n, dtype, rand)

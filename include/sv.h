@@ -118,6 +118,9 @@ typedef struct sv_plan_stats {
     int64_t n_block_passes; /* of which: block passes (several gates each) */
     int64_t block_qubits;   /* qubits per on-chip block (b) */
     double bytes_moved;     /* algorithmic HBM bytes of all passes */
+    int64_t n_stages;       /* register windows over all block passes */
+    int64_t n_ops;          /* block-pass ops (after merging diagonal runs) */
+    int64_t n_phase_ops;    /* merged diagonal runs */
 } sv_plan_stats;
 
 typedef struct sv_state_t* sv_state;
@@ -125,7 +128,7 @@ typedef struct sv_state_t* sv_state;
 /* Create a handle for an n-qubit state (Sec. II Eq. 1-2: 2^n amplitudes of
  * S_state bytes).
  *   n_qubits   1..34 (34 only for SV_C64 in practice: 2^34 * 8 = 128 GiB)
- *   device_buf device memory of >= 2^n * S_state bytes, 256-byte aligned,
+ *   device_buf device memory of >= 2^n * S_state bytes, 16-byte aligned,
  *              owned by the caller (e.g. a torch tensor) and not freed by the
  *              library; NULL makes the library allocate (freed by sv_free)
  *   hip_stream hipStream_t the handle enqueues on (NULL = default stream)

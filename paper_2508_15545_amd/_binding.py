@@ -47,6 +47,9 @@ class SvPlanStats(ctypes.Structure):
         ("n_block_passes", ctypes.c_int64),
         ("block_qubits", ctypes.c_int64),
         ("bytes_moved", ctypes.c_double),
+        ("n_stages", ctypes.c_int64),
+        ("n_ops", ctypes.c_int64),
+        ("n_phase_ops", ctypes.c_int64),
     ]
 
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqvec.so")
-SOURCES = ["kernels.hip", "gates.cpp", "planner.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_block.hip", "gates.cpp", "planner.cpp", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept off: the compiler must not form them.

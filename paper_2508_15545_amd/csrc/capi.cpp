@@ -2,6 +2,7 @@
 // upload, pass execution, FP64 reductions and the adjoint sweep.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -274,23 +275,30 @@ std::vector<TermBatch> batch_terms(const sv_pauli* terms, int n_terms)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+struct TableOffsets {
+    std::vector<size_t> hdr;  // byte offset of each block pass's header
+    size_t stages = 0, ops = 0, mats = 0, phase = 0;
+};
+
 template <typename T>
-sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, std::vector<size_t>* hdr_off,
-                        size_t* ops_off, size_t* mats_off)
+sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, TableOffsets* off)
 {
-    size_t n_hdr = 0, n_ops = 0, n_mats = 0;
+    size_t n_hdr = 0, n_st = 0, n_ops = 0, n_mats = 0, n_ph = 0;
     for (const auto& p : passes)
         if (p.kind == PlanPass::BLOCK) {
             n_hdr++;
+            n_st += p.stages.size();
             n_ops += p.ops.size();
             n_mats += p.mats.size();
+            n_ph += p.phase.size();
         }
-    hdr_off->clear();
+    off->hdr.clear();
     if (n_hdr == 0) return SV_OK;
-    const size_t b_hdr = n_hdr * sizeof(PassHdr);
-    *ops_off = align_up(b_hdr, 256);
-    *mats_off = align_up(*ops_off + n_ops * sizeof(TileOp), 256);
-    const size_t total = *mats_off + n_mats * sizeof(T);
+    off->stages = align_up(n_hdr * sizeof(PassHdr), 256);
+    off->ops = align_up(off->stages + n_st * sizeof(StageHdr), 256);
+    off->mats = align_up(off->ops + n_ops * sizeof(TileOp), 256);
+    off->phase = align_up(off->mats + n_mats * sizeof(T), 256);
+    const size_t total = off->phase + n_ph * sizeof(PhaseTerm);
 
     if (s->table_pending) {  // the staging buffer may still feed the last copy
         HIP_TRY(hipEventSynchronize(s->table_done));
@@ -311,21 +319,27 @@ sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, std::ve
     if (st != SV_OK) return st;
 
     PassHdr* H = reinterpret_cast<PassHdr*>(s->h_table);
-    TileOp* O = reinterpret_cast<TileOp*>(s->h_table + *ops_off);
-    T* M = reinterpret_cast<T*>(s->h_table + *mats_off);
-    size_t ih = 0, io = 0, im = 0;
+    StageHdr* S = reinterpret_cast<StageHdr*>(s->h_table + off->stages);
+    TileOp* O = reinterpret_cast<TileOp*>(s->h_table + off->ops);
+    T* M = reinterpret_cast<T*>(s->h_table + off->mats);
+    PhaseTerm* P = reinterpret_cast<PhaseTerm*>(s->h_table + off->phase);
+    size_t ih = 0, is = 0, io = 0, im = 0, ip = 0;
     for (const auto& p : passes) {
         if (p.kind != PlanPass::BLOCK) continue;
         PassHdr h = p.hdr;
         h.op_begin = (int32_t)io;
+        h.stage_begin = (int32_t)is;
+        h.n_stages = (int32_t)p.stages.size();
         H[ih] = h;
-        hdr_off->push_back(ih * sizeof(PassHdr));
+        off->hdr.push_back(ih * sizeof(PassHdr));
         ih++;
+        for (const StageHdr& sh : p.stages) S[is++] = sh;
         for (const TileOp& op : p.ops) {
             TileOp t = op;
-            t.mat += (int32_t)im;
+            t.mat += (int32_t)(t.kind == T_PHASE ? ip : im);
             O[io++] = t;
         }
+        for (const PhaseTerm& pt : p.phase) P[ip++] = pt;
         for (const cd& v : p.mats) {
             using R = std::remove_reference_t<decltype(M[0].x)>;
             T e;
@@ -346,14 +360,15 @@ template <typename T>
 sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1, int n_states,
                    std::vector<int>* grad_rows_per_pass, double* d_gvals)
 {
-    std::vector<size_t> hdr_off;
-    size_t ops_off = 0, mats_off = 0;
-    sv_status st = upload_tables<T>(s, passes, &hdr_off, &ops_off, &mats_off);
+    TableOffsets off;
+    sv_status st = upload_tables<T>(s, passes, &off);
     if (st != SV_OK) return st;
     const unsigned char* base = reinterpret_cast<const unsigned char*>(s->d_table);
     const PassHdr* d_hdr = reinterpret_cast<const PassHdr*>(base);
-    const TileOp* d_ops = reinterpret_cast<const TileOp*>(base + ops_off);
-    const T* d_mats = reinterpret_cast<const T*>(base + mats_off);
+    const StageHdr* d_stages = reinterpret_cast<const StageHdr*>(base + off.stages);
+    const TileOp* d_ops = reinterpret_cast<const TileOp*>(base + off.ops);
+    const T* d_mats = reinterpret_cast<const T*>(base + off.mats);
+    const PhaseTerm* d_phase = reinterpret_cast<const PhaseTerm*>(base + off.phase);
 
     size_t ih = 0;
     int64_t gval_off = 0;
@@ -369,8 +384,14 @@ sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1
             }
             {
                 LaunchTimer tm(s, n_states == 2 ? KF_ADJ_BLOCK : KF_BLOCK);
-                HIP_TRY((launch_block_pass<T>(s0, s1, s->n, n_states, d_hdr + hdr_off[ih] / sizeof(PassHdr), d_ops,
-                                              d_mats, b, s->d_part, nblocks, s->stream)));
+                const PassHdr* h = d_hdr + off.hdr[ih] / sizeof(PassHdr);
+                if (!pp.stages.empty()) {
+                    HIP_TRY((launch_block_reg<T>(s0, s1, s->n, n_states, h, d_stages, d_ops, d_mats, d_phase, b,
+                                                 s->d_part, nblocks, s->stream)));
+                } else {
+                    HIP_TRY((launch_block_pass<T>(s0, s1, s->n, n_states, h, d_ops, d_mats, b, s->d_part, nblocks,
+                                                  s->stream)));
+                }
             }
             ih++;
             if (rows > 0) {
@@ -404,6 +425,8 @@ sv_status dispatch(sv_state s, F&& f)
     return f(static_cast<f2*>(s->buf));
 }
 
+bool g_reg_kernel = true;  // register-resident block passes (QVEC_BLOCK_KERNEL=lds turns them off)
+
 PlanOptions plan_options(int n, size_t elem, int n_states)
 {
     PlanOptions o;
@@ -411,6 +434,11 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.b = default_block_qubits(n, (int)elem, n_states);
     // keep 128-byte runs contiguous in memory: 8 complex128 / 16 complex64
     o.coalesce = elem == 16 ? 3 : 4;
+    const char* env = std::getenv("QVEC_BLOCK_KERNEL");
+    const bool reg = g_reg_kernel && !(env && std::strcmp(env, "lds") == 0);
+    o.reg_bits = reg ? reg_bits_for((int)elem, n_states) : 0;
+    const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given inside a pass
+    o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     return o;
 }
 
@@ -657,6 +685,9 @@ sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gate
             out->n_passes++;
             if (p.kind == PlanPass::BLOCK) out->n_block_passes++;
             out->bytes_moved += p.bytes;
+            out->n_stages += (int64_t)p.stages.size();
+            out->n_ops += (int64_t)p.ops.size();
+            for (const auto& op : p.ops) out->n_phase_ops += op.kind == T_PHASE ? 1 : 0;
         }
     } catch (const std::exception& e) {
         return fail(SV_EINVAL, std::string("planner: ") + e.what());

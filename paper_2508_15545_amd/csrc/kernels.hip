@@ -4,134 +4,9 @@
 // Amplitudes are native 2-vectors (re, im): d2 (complex128, 16 B) or f2
 // (complex64, 8 B), so every amplitude moves with one 16-/8-byte access.
 // All indices are 64-bit (2^34 amplitudes at most).
-#include "qv_internal.h"
-
-#include <hip/hip_runtime.h>
+#include "device_common.h"
 
 namespace qv {
-
-template <typename T> struct RealOf;
-template <> struct RealOf<d2> { using type = double; };
-template <> struct RealOf<f2> { using type = float; };
-
-constexpr int kThreads = 256;
-
-// ------------------------------------------------------------- helpers ---
-
-template <typename T>
-__device__ __forceinline__ T cmul(T a, T b)
-{
-    T r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-
-// u0 * x + u1 * y
-template <typename T>
-__device__ __forceinline__ T cmul2(T u0, T x, T u1, T y)
-{
-    T r;
-    r.x = u0.x * x.x - u0.y * x.y + u1.x * y.x - u1.y * y.y;
-    r.y = u0.x * x.y + u0.y * x.x + u1.x * y.y + u1.y * y.x;
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T* p)
-{
-    return __builtin_nontemporal_load(p);
-}
-
-template <typename T>
-__device__ __forceinline__ void st_nt(T* p, T v)
-{
-    __builtin_nontemporal_store(v, p);
-}
-
-// Insert a zero bit at each position of pos[0..cnt) (ascending final
-// positions) into v.
-struct Ins {
-    int cnt;
-    int pos[5];
-};
-
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t v, const Ins& ins)
-{
-#pragma unroll
-    for (int j = 0; j < 5; j++) {
-        if (j < ins.cnt) {
-            const int p = ins.pos[j];
-            const uint64_t lo = v & ((1ull << p) - 1);
-            v = ((v >> p) << (p + 1)) | lo;
-        }
-    }
-    return v;
-}
-
-static Ins make_ins(uint64_t mask)
-{
-    Ins r{};
-    r.cnt = 0;
-    for (int q = 0; q < 64 && mask; q++) {
-        if (mask & (1ull << q)) {
-            r.pos[r.cnt++] = q;
-            mask &= ~(1ull << q);
-        }
-    }
-    return r;
-}
-
-template <typename T>
-static T to_dev(cd v)
-{
-    T r;
-    r.x = (typename RealOf<T>::type)v.real();
-    r.y = (typename RealOf<T>::type)v.imag();
-    return r;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Block-wide sum in a fixed order (waves reduced by shuffles, then wave 0
-// adds the per-wave results in index order). Result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red)
-{
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    double t = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += red[i];
-    __syncthreads();
-    return t;
-}
-
-__device__ __forceinline__ double block_max(double v, double* red)
-{
-    v = wave_max(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    double t = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); i++) t = fmax(t, red[i]);
-    __syncthreads();
-    return t;
-}
 
 static unsigned grid_for(uint64_t items, uint64_t per_block)
 {
@@ -409,6 +284,40 @@ __global__ __launch_bounds__(kThreads) void k_block(T* __restrict__ s0, T* __res
                     const T x = lds1[i0], y = lds1[i1];
                     lds1[i0] = cmul2(u00, x, u01, y);
                     lds1[i1] = cmul2(u10, x, u11, y);
+                }
+            }
+        } else if (op.kind == T_XPERM) {
+            const int a = op.a;
+            const int lowm = (1 << a) - 1;
+            for (int p = tid; p < (nloc >> 1); p += kThreads) {
+                const int i0 = ((p & ~lowm) << 1) | (p & lowm);
+                if ((i0 & lc) != lc) continue;
+                const int i1 = i0 | (1 << a);
+                const T x = lds0[i0];
+                lds0[i0] = lds0[i1];
+                lds0[i1] = x;
+                if (NS == 2) {
+                    const T y = lds1[i0];
+                    lds1[i0] = lds1[i1];
+                    lds1[i1] = y;
+                }
+            }
+        } else if (op.kind == T_SWAP) {
+            const int a = op.a, c = op.c;
+            const int lo = a < c ? a : c, hi = a < c ? c : a;
+            const int mlo = (1 << lo) - 1, mhi = (1 << hi) - 1;
+            for (int p = tid; p < (nloc >> 2); p += kThreads) {
+                int i0 = ((p & ~mlo) << 1) | (p & mlo);
+                i0 = ((i0 & ~mhi) << 1) | (i0 & mhi);
+                if ((i0 & lc) != lc) continue;
+                const int ia = i0 | (1 << a), ic = i0 | (1 << c);
+                const T x = lds0[ia];
+                lds0[ia] = lds0[ic];
+                lds0[ic] = x;
+                if (NS == 2) {
+                    const T y = lds1[ia];
+                    lds1[ia] = lds1[ic];
+                    lds1[ic] = y;
                 }
             }
         } else if (op.kind == T_DENSE2) {

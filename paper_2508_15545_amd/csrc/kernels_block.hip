@@ -1,0 +1,552 @@
+// Register-resident block pass for gfx950.
+//
+// One workgroup owns a block of 2^b amplitudes (the indices that agree
+// outside the pass's local qubits; block storage of QVecOpt Sec. III.C,
+// generalised to any qubit set). Each thread holds R = 2^r of them in
+// registers: the ones whose local positions in the current window W (r
+// positions) vary while the other b - r positions are fixed by the thread
+// index. Gates acting densely inside the window are applied in registers
+// (pairs and quadruples of Sec. III.A Eq. 5 / Sec. III.C are register pairs
+// and quadruples of one thread); diagonal gates and controls may use any
+// bit because each amplitude knows its index. Moving to the next window is a
+// transpose through LDS (write all, barrier, read all), so LDS traffic is
+// one round trip per window change instead of one per gate, and HBM sees
+// the block once per pass.
+//
+// The block is loaded and stored with the natural mapping (lanes run over
+// the lowest local positions, which hold the lowest qubits and so
+// contiguous runs of memory); the planner starts and, when it can, ends on
+// that window.
+#include "device_common.h"
+
+namespace qv {
+
+// 16-byte (complex128) or 8-byte (complex64) LDS slots; XOR-fold the higher
+// index bits into the bits that select the slot within a 256-byte row so
+// that lanes striding by a power of two land in different banks.
+template <typename T>
+__device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
+{
+    constexpr int e = sizeof(T) == 16 ? 4 : 5;
+    constexpr uint32_t m = (1u << e) - 1;
+    const uint32_t h = l >> e;
+    return l ^ ((h ^ (h >> e) ^ (h >> (2 * e))) & m);
+}
+
+// Local index bits contributed by the thread index when the window is W:
+// thread bit i goes to the i-th lowest position outside W.
+__device__ __forceinline__ uint32_t thread_part(uint32_t wmask, int b, int tid)
+{
+    uint32_t tl = 0;
+    int i = 0;
+    for (int p = 0; p < b; p++) {
+        if (!((wmask >> p) & 1u)) {
+            tl |= (uint32_t)((tid >> i) & 1) << p;
+            i++;
+        }
+    }
+    return tl;
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t window_part(int k, const int (&w)[kMaxRegBits])
+{
+    uint32_t l = 0;
+#pragma unroll
+    for (int j = 0; j < RB; j++) l |= (uint32_t)((k >> j) & 1) << w[j];
+    return l;
+}
+
+// Transpose the thread's registers from window w_old to w_new through LDS.
+// The swizzle is linear over XOR and the thread and window parts of an index
+// have disjoint bits, so slot(tl | wl) = slot(tl) ^ slot(wl): one per-thread
+// term and one uniform term per register.
+template <typename T, int RB, int NS>
+__device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, uint32_t tl_old,
+                                         const int (&w_old)[kMaxRegBits], uint32_t tl_new,
+                                         const int (&w_new)[kMaxRegBits])
+{
+    constexpr int R = 1 << RB;
+    unsigned char* base = reinterpret_cast<unsigned char*>(lds);
+    const uint32_t so = lds_swizzle<T>(tl_old) * (uint32_t)sizeof(T);
+    const uint32_t sn = lds_swizzle<T>(tl_new) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        // uniform part, kept in a scalar register
+        const uint32_t wk = __builtin_amdgcn_readfirstlane(lds_swizzle<T>(window_part<RB>(k, w_old)) * (uint32_t)sizeof(T));
+        const uint32_t off = so ^ wk;
+#pragma unroll
+        for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const uint32_t wk = __builtin_amdgcn_readfirstlane(lds_swizzle<T>(window_part<RB>(k, w_new)) * (uint32_t)sizeof(T));
+        const uint32_t off = sn ^ wk;
+#pragma unroll
+        for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
+    }
+    __syncthreads();
+}
+
+// Control mask of an op, one bit per register: its local control bits are all set.
+template <int RB>
+__device__ __forceinline__ uint32_t ctrl_bits(uint32_t lctrl, uint32_t tl, const int (&w)[kMaxRegBits])
+{
+    uint32_t cm = 0;
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) cm |= (((tl | window_part<RB>(k, w)) & lctrl) == lctrl ? 1u : 0u) << k;
+    return cm;
+}
+
+template <typename T, int RB, int NS, int J, bool CTRL>
+__device__ __forceinline__ void reg_dense1(T (&v)[NS][1 << RB], T u00, T u01, T u10, T u11, uint32_t cm)
+{
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if (k & (1 << J)) continue;
+        const int k1 = k | (1 << J);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const T x = v[s][k], y = v[s][k1];
+            const T a = cmul2(u00, x, u01, y), c = cmul2(u10, x, u11, y);
+            if (CTRL) {
+                const bool on = (cm >> k) & 1u;
+                v[s][k] = on ? a : x;
+                v[s][k1] = on ? c : y;
+            } else {
+                v[s][k] = a;
+                v[s][k1] = c;
+            }
+        }
+    }
+}
+
+template <typename T, int RB, int NS, int J, bool CTRL>
+__device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm)
+{
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if (k & (1 << J)) continue;
+        const int k1 = k | (1 << J);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const T x = v[s][k], y = v[s][k1];
+            if (CTRL) {
+                const bool on = (cm >> k) & 1u;
+                v[s][k] = on ? y : x;
+                v[s][k1] = on ? x : y;
+            } else {
+                v[s][k] = y;
+                v[s][k1] = x;
+            }
+        }
+    }
+}
+
+// CNOT with target window bit JT and control window bit JC: swap the
+// register pairs whose control bit is set.
+template <typename T, int RB, int NS, int JT, int JC>
+__device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB])
+{
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if ((k & (1 << JT)) || !(k & (1 << JC))) continue;
+        const int k1 = k | (1 << JT);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const T x = v[s][k];
+            v[s][k] = v[s][k1];
+            v[s][k1] = x;
+        }
+    }
+}
+
+template <typename T, int RB, int NS, int J0, int J1>
+__device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restrict__ m, uint32_t cm, bool ctrl)
+{
+    T u[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) u[e] = m[e];
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if (k & ((1 << J0) | (1 << J1))) continue;
+        const int idx[4] = {k, k | (1 << J0), k | (1 << J1), k | (1 << J0) | (1 << J1)};
+        const bool on = !ctrl || ((cm >> k) & 1u);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            T x[4], w[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) x[e] = v[s][idx[e]];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                w[r] = cmul2(u[4 * r], x[0], u[4 * r + 1], x[1]);
+                const T t = cmul2(u[4 * r + 2], x[2], u[4 * r + 3], x[3]);
+                w[r].x += t.x;
+                w[r].y += t.y;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[s][idx[e]] = on ? w[e] : x[e];
+        }
+    }
+}
+
+template <typename T, int RB, int NS, int J0, int J1>
+__device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, bool ctrl)
+{
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if (k & ((1 << J0) | (1 << J1))) continue;
+        const int a = k | (1 << J0), c = k | (1 << J1);
+        const bool on = !ctrl || ((cm >> k) & 1u);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const T x = v[s][a], y = v[s][c];
+            v[s][a] = on ? y : x;
+            v[s][c] = on ? x : y;
+        }
+    }
+}
+
+// Im <lambda|G|phi> contributions of the thread's registers for G = X or Y
+// on window bit J (v[0] = phi, v[1] = lambda).
+template <typename T, int RB, int J>
+__device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], int gen)
+{
+    double acc = 0;
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        const int p = k ^ (1 << J);
+        const T f = v[0][p], m = v[1][k];
+        const double re = (double)m.x * (double)f.x + (double)m.y * (double)f.y;
+        const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+        const bool bit = (k >> J) & 1;
+        // X: Im(conj(m) f); Y: (Y phi)_l = (bit ? i : -i) phi_{l ^ J}
+        acc += gen == GEN_X ? im : (bit ? re : -re);
+    }
+    return acc;
+}
+
+#define QV_J1_CASES(F)                                   \
+    case 0: F(0); break;                                 \
+    case 1: F(1); break;                                 \
+    case 2: F(2); break;                                 \
+    case 3: if constexpr (RB > 3) { F(3); } break;       \
+    case 4: if constexpr (RB > 4) { F(4); } break;
+
+template <typename T, int RB, int NS>
+__global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
+                                                   const PassHdr* __restrict__ hdr,
+                                                   const StageHdr* __restrict__ stages,
+                                                   const TileOp* __restrict__ ops, const T* __restrict__ mats,
+                                                   const PhaseTerm* __restrict__ phase, double* __restrict__ gpart,
+                                                   int64_t gstride)
+{
+    constexpr int R = 1 << RB;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[NS == 2 ? kMaxGradPerPass * 8 : 1];
+
+    const int b = hdr->b;
+    const int nloc = 1 << b;
+    const int tb = b - RB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint64_t blk = blockIdx.x;
+
+    uint64_t base = 0;
+    for (int j = 0; j < hdr->n_outer; j++) base |= ((blk >> j) & 1ull) << hdr->outer_q[j];
+
+    // Natural mapping: thread bits on positions 0..tb-1, registers on tb..b-1.
+    int wn[kMaxRegBits];
+#pragma unroll
+    for (int j = 0; j < kMaxRegBits; j++) wn[j] = j < RB ? tb + j : 0;
+    const uint32_t natural = ((1u << RB) - 1) << tb;
+    uint64_t gt = base;
+    for (int j = 0; j < tb; j++) gt |= (uint64_t)((tid >> j) & 1) << hdr->local_q[j];
+    int qr[RB];  // global qubits of the natural window
+#pragma unroll
+    for (int j = 0; j < RB; j++) qr[j] = hdr->local_q[tb + j];
+
+    T v[NS][R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        uint64_t g = gt;
+#pragma unroll
+        for (int j = 0; j < RB; j++)
+            if ((k >> j) & 1) g |= 1ull << qr[j];
+        v[0][k] = ld_nt(s0 + g);
+        if (NS == 2) v[NS - 1][k] = ld_nt(s1 + g);
+    }
+
+    uint32_t cur_mask = natural;
+    int cur_w[kMaxRegBits];
+#pragma unroll
+    for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = wn[j];
+    uint32_t cur_tl = tid;  // natural: thread bits are the low positions
+
+    const TileOp* po = ops + hdr->op_begin;
+    const int n_stages = hdr->n_stages;
+    for (int si = 0; si < n_stages; si++) {
+        const StageHdr sh = stages[hdr->stage_begin + si];
+        if (sh.wmask != cur_mask) {
+            int w_new[kMaxRegBits];
+#pragma unroll
+            for (int j = 0; j < kMaxRegBits; j++) w_new[j] = sh.w[j];
+            const uint32_t tl_new = thread_part(sh.wmask, b, tid);
+            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_new, w_new);
+            cur_mask = sh.wmask;
+            cur_tl = tl_new;
+#pragma unroll
+            for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
+        }
+        for (int o = 0; o < sh.n_ops; o++) {
+            const TileOp op = po[sh.op_begin + o];
+            if ((base & op.gctrl) != op.gctrl) continue;  // uniform over the block
+            const bool ctrl = op.lctrl != 0;
+            const bool cx_in_window = op.kind == T_XPERM && op.j1 >= 0 && op.c >= 0 && op.lctrl == (1u << op.c);
+            const uint32_t cm = (ctrl && !cx_in_window) ? ctrl_bits<RB>(op.lctrl, cur_tl, cur_w) : ~0u;
+            switch (op.kind) {
+            case T_DENSE1: {
+                const T u00 = mats[op.mat], u01 = mats[op.mat + 1], u10 = mats[op.mat + 2], u11 = mats[op.mat + 3];
+#define QV_D1(J)                                                                      \
+    if (ctrl) reg_dense1<T, RB, NS, J, true>(v, u00, u01, u10, u11, cm);              \
+    else reg_dense1<T, RB, NS, J, false>(v, u00, u01, u10, u11, cm);
+                switch (op.j0) { QV_J1_CASES(QV_D1) }
+#undef QV_D1
+                break;
+            }
+            case T_XPERM: {
+                if (op.j1 >= 0 && op.c >= 0 && op.lctrl == (1u << op.c)) {
+                    // control inside the window: a fixed register permutation
+#define QV_CX(A, B)                                                       \
+    case A * 8 + B:                                                       \
+        if constexpr (A < RB && B < RB && A != B) reg_cx<T, RB, NS, A, B>(v); \
+        break;
+                    switch (op.j0 * 8 + op.j1) {
+                        QV_CX(0, 1) QV_CX(0, 2) QV_CX(0, 3) QV_CX(0, 4)
+                        QV_CX(1, 0) QV_CX(1, 2) QV_CX(1, 3) QV_CX(1, 4)
+                        QV_CX(2, 0) QV_CX(2, 1) QV_CX(2, 3) QV_CX(2, 4)
+                        QV_CX(3, 0) QV_CX(3, 1) QV_CX(3, 2) QV_CX(3, 4)
+                        QV_CX(4, 0) QV_CX(4, 1) QV_CX(4, 2) QV_CX(4, 3)
+                    default: break;
+                    }
+#undef QV_CX
+                    break;
+                }
+#define QV_X(J)                                            \
+    if (ctrl) reg_xperm<T, RB, NS, J, true>(v, cm);        \
+    else reg_xperm<T, RB, NS, J, false>(v, cm);
+                switch (op.j0) { QV_J1_CASES(QV_X) }
+#undef QV_X
+                break;
+            }
+            case T_DENSE2:
+            case T_SWAP: {
+                const int pair = op.j0 * kMaxRegBits + op.j1;
+                const bool dense = op.kind == T_DENSE2;
+                const T* m = mats + op.mat;
+#define QV_P(A, B)                                                                     \
+    case A * kMaxRegBits + B:                                                           \
+        if constexpr (B < RB) {                                                         \
+            if (dense) reg_dense2<T, RB, NS, A, B>(v, m, cm, ctrl);                     \
+            else reg_swap<T, RB, NS, A, B>(v, cm, ctrl);                                \
+        }                                                                               \
+        break;
+                switch (pair) {
+                    QV_P(0, 1) QV_P(0, 2) QV_P(0, 3) QV_P(0, 4) QV_P(1, 2)
+                    QV_P(1, 3) QV_P(1, 4) QV_P(2, 3) QV_P(2, 4) QV_P(3, 4)
+                default: break;
+                }
+#undef QV_P
+                break;
+            }
+            case T_DIAG: {
+                const T d0 = mats[op.mat], d1 = mats[op.mat + 1], dd2 = mats[op.mat + 2], d3 = mats[op.mat + 3];
+                const int a = op.a, c = op.c;
+                const int ua = a < 0 ? (op.oa >= 0 ? (int)((base >> op.oa) & 1) : 0) : 0;
+                const int uc = c < 0 ? (op.oc >= 0 ? (int)((base >> op.oc) & 1) : 0) : 0;
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
+                    const int ba = a >= 0 ? (int)((l >> a) & 1) : ua;
+                    const int bc = c >= 0 ? (int)((l >> c) & 1) : uc;
+                    const int sel = ba + 2 * bc;
+                    const T d = sel == 0 ? d0 : sel == 1 ? d1 : sel == 2 ? dd2 : d3;
+                    const bool on = !ctrl || ((cm >> k) & 1u);
+#pragma unroll
+                    for (int s = 0; s < NS; s++) {
+                        const T x = v[s][k];
+                        const T y = cmul(d, x);
+                        v[s][k] = on ? y : x;
+                    }
+                }
+                break;
+            }
+            case T_PHASE: {
+                // A: the part of the angle fixed for this thread; eff[j] and
+                // qq[j][j2]: coefficients of window bits j and j & j2.
+                double A = 0, eff[RB], qq[RB][RB];
+#pragma unroll
+                for (int j = 0; j < RB; j++) {
+                    eff[j] = 0;
+#pragma unroll
+                    for (int j2 = 0; j2 < RB; j2++) qq[j][j2] = 0;
+                }
+                const PhaseTerm* pt = phase + op.mat;
+                for (int t = 0; t < op.cnt; t++) {
+                    const PhaseTerm term = pt[t];
+                    auto bitval = [&](int p) -> int {
+                        return p < 64 ? (int)((cur_tl >> p) & 1u) : (int)((base >> (p - 64)) & 1ull);
+                    };
+                    if (term.kind == PH_THREAD) {
+                        int bv = bitval(term.p1);
+                        if (term.p2 >= 0) bv &= bitval(term.p2);
+                        A += bv ? term.th : 0.0;
+                    } else if (term.kind == PH_MIXED) {
+                        const double x = bitval(term.p1) ? term.th : 0.0;
+#pragma unroll
+                        for (int j = 0; j < RB; j++)
+                            if (j == term.j) eff[j] += x;
+                    } else if (term.kind == PH_WLIN) {
+#pragma unroll
+                        for (int j = 0; j < RB; j++)
+                            if (j == term.j) eff[j] += term.th;
+                    } else if (term.kind == PH_WQUAD) {
+#pragma unroll
+                        for (int j = 0; j < RB; j++)
+#pragma unroll
+                            for (int j2 = j + 1; j2 < RB; j2++)
+                                if (j == term.j && j2 == term.j2) qq[j][j2] += term.th;
+                    } else {
+                        A += term.th;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    double ang = A;
+#pragma unroll
+                    for (int j = 0; j < RB; j++) {
+                        if (!((k >> j) & 1)) continue;
+                        ang += eff[j];
+#pragma unroll
+                        for (int j2 = j + 1; j2 < RB; j2++)
+                            if ((k >> j2) & 1) ang += qq[j][j2];
+                    }
+                    ang -= rint(ang);  // turns, in [-1/2, 1/2]
+                    T f;
+                    if constexpr (sizeof(T) == 16) {
+                        double sn, cs;
+                        sincospi(2.0 * ang, &sn, &cs);
+                        f.x = cs;
+                        f.y = sn;
+                    } else {
+                        float sn, cs;
+                        sincospif((float)(2.0 * ang), &sn, &cs);
+                        f.x = cs;
+                        f.y = sn;
+                    }
+#pragma unroll
+                    for (int s = 0; s < NS; s++) v[s][k] = cmul(f, v[s][k]);
+                }
+                break;
+            }
+            case T_GRAD: {
+                if constexpr (NS == 2) {
+                    double acc = 0;
+                    if (op.gen == GEN_Z) {
+                        const int a = op.a;
+                        const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
+#pragma unroll
+                        for (int k = 0; k < R; k++) {
+                            const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
+                            const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
+                            const T f = v[0][k], m = v[1][k];
+                            const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+                            acc += bit ? -im : im;
+                        }
+                    } else {
+#define QV_G(J) acc = reg_grad_xy<T, RB, J>(v, op.gen);
+                        switch (op.j0) { QV_J1_CASES(QV_G) }
+#undef QV_G
+                    }
+                    acc = wave_sum(acc);
+                    if (lane == 0) red[op.slot * 8 + wave] = acc;
+                }
+                break;
+            }
+            default: break;
+            }
+        }
+    }
+
+    if (cur_mask != natural) {
+        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, (uint32_t)tid, wn);
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        uint64_t g = gt;
+#pragma unroll
+        for (int j = 0; j < RB; j++)
+            if ((k >> j) & 1) g |= 1ull << qr[j];
+        st_nt(s0 + g, v[0][k]);
+        if (NS == 2) st_nt(s1 + g, v[NS - 1][k]);
+    }
+
+    if constexpr (NS == 2) {
+        const int ng = hdr->n_grad;
+        if (ng > 0) {
+            __syncthreads();
+            const int nw = (int)(blockDim.x >> 6);
+            for (int sl = tid; sl < ng; sl += blockDim.x) {
+                double t = 0;
+                for (int w = 0; w < nw; w++) t += red[sl * 8 + w];
+                gpart[(int64_t)sl * gstride + (int64_t)blk] = t;
+            }
+        }
+    }
+}
+
+#undef QV_J1_CASES
+
+template <typename T, int RB, int NS>
+static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
+                               const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
+                               int64_t gs, hipStream_t st)
+{
+    static size_t attr_bytes = 0;
+    const size_t lds = (size_t)NS * ((size_t)1 << b) * sizeof(T);
+    if (lds > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_block_reg<T, RB, NS>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_bytes = lds;
+    }
+    const uint64_t nblocks = 1ull << (n - b);
+    const unsigned threads = 1u << (b - RB);
+    hipLaunchKernelGGL((k_block_reg<T, RB, NS>), dim3((unsigned)nblocks), dim3(threads), lds, st, s0, s1, d_hdr,
+                       d_stages, d_ops, d_mats, d_phase, gp, gs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const StageHdr* d_stages,
+                            const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
+                            int64_t gs, hipStream_t st)
+{
+    if (n_states == 2) {
+        constexpr int RB = sizeof(T) == 16 ? 3 : 4;
+        if (b - RB < 6 || b - RB > 9) return hipErrorInvalidValue;  // whole waves, at most 512 threads
+        return launch_reg_t<T, RB, 2>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+    }
+    constexpr int RB = 4;
+    if (b - RB < 6 || b - RB > 9) return hipErrorInvalidValue;
+    return launch_reg_t<T, RB, 1>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+}
+
+template hipError_t launch_block_reg<d2>(d2*, d2*, int, int, const PassHdr*, const StageHdr*, const TileOp*,
+                                         const d2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
+template hipError_t launch_block_reg<f2>(f2*, f2*, int, int, const PassHdr*, const StageHdr*, const TileOp*,
+                                         const f2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
+
+}  // namespace qv

@@ -18,8 +18,11 @@
 // So the pass result equals applying the gates one by one (Sec. III.E: one
 // traversal for a batch of gates, same result as gate by gate).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <stdexcept>
+#include <utility>
 
 #include "gates.h"
 #include "qv_internal.h"
@@ -33,6 +36,8 @@ int default_block_qubits(int n, int elem_bytes, int n_states)
     const int lb = (elem_bytes == 16 ? 12 : 13) - (n_states == 2 ? 1 : 0);
     return std::min(n, lb);
 }
+
+int reg_bits_for(int elem_bytes, int n_states) { return (n_states == 2 && elem_bytes == 16) ? 3 : 4; }
 
 namespace {
 
@@ -60,6 +65,469 @@ ItemBits bits_of(const PlanItem& it)
 double sweep_bytes(const HostGate& g, int n, int elem)
 {
     return 2.0 * std::ldexp(1.0, n - popc(g.ctrl)) * elem;
+}
+
+bool is_pauli_x(const HostGate& g)
+{
+    return g.m[0] == 0.0 && g.m[1] == 1.0 && g.m[2] == 1.0 && g.m[3] == 0.0;
+}
+
+bool is_swap(const HostGate& g)
+{
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            const bool one = (r == 0 && c == 0) || (r == 3 && c == 3) || (r == 1 && c == 2) || (r == 2 && c == 1);
+            if (g.m[4 * r + c] != (one ? 1.0 : 0.0)) return false;
+        }
+    return true;
+}
+
+// Local positions an op acts on non-diagonally / diagonally.
+void op_positions(const TileOp& t, uint32_t* dense, uint32_t* diag)
+{
+    *dense = 0;
+    *diag = t.lctrl;
+    switch (t.kind) {
+    case T_DENSE1:
+    case T_XPERM: *dense = 1u << t.a; break;
+    case T_DENSE2:
+    case T_SWAP: *dense = (1u << t.a) | (1u << t.c); break;
+    case T_DIAG:
+        if (t.a >= 0) *diag |= 1u << t.a;
+        if (t.c >= 0) *diag |= 1u << t.c;
+        break;
+    case T_GRAD:
+        if (t.gen == GEN_Z) {
+            if (t.a >= 0) *diag |= 1u << t.a;
+        } else {
+            *dense = 1u << t.a;
+        }
+        break;
+    default: break;
+    }
+}
+
+int window_index(const StageHdr& st, int r, int pos)
+{
+    for (int j = 0; j < r; j++)
+        if (st.w[j] == pos) return j;
+    return -1;
+}
+
+// Split a block pass into register stages. Each stage holds a window of r
+// local positions in every thread's registers; the ops of the stage act
+// densely only inside the window (diagonal ops and controls may use any
+// position). Ops move between stages only past ops they commute with, by the
+// same rule as gates between passes. The first window is the one the block
+// is loaded with (the top r positions), and leftover window slots are filled
+// with those positions too, so that the last stage often needs no exchange
+// before the store.
+void plan_stages(PlanPass& pp, int b, int r)
+{
+    const uint32_t natural = ((1u << r) - 1) << (b - r);
+    std::vector<TileOp>& ops = pp.ops;
+    std::vector<uint32_t> dn(ops.size()), dg(ops.size());
+    for (size_t i = 0; i < ops.size(); i++) op_positions(ops[i], &dn[i], &dg[i]);
+    std::vector<char> done(ops.size(), 0);
+    std::vector<TileOp> out;
+    out.reserve(ops.size());
+    pp.stages.clear();
+    size_t first = 0;
+    bool first_stage = true;
+    while (true) {
+        while (first < ops.size() && done[first]) first++;
+        if (first >= ops.size()) break;
+        uint32_t W = first_stage ? natural : 0;
+        uint32_t bd = 0, bg = 0;
+        std::vector<size_t> taken;
+        for (size_t i = first; i < ops.size(); i++) {
+            if (done[i]) continue;
+            bool ok = !(dn[i] & (bd | bg)) && !(dg[i] & bd);
+            if (ok) {
+                const uint32_t need = dn[i] & ~W;
+                if (popc(W | need) > r) ok = false;
+                else W |= need;
+            }
+            if (ok) {
+                taken.push_back(i);
+            } else {
+                bd |= dn[i];
+                bg |= dg[i];
+            }
+        }
+        if (taken.empty()) {
+            if (!first_stage) throw std::runtime_error("stage planner made no progress");
+            first_stage = false;
+            continue;
+        }
+        first_stage = false;
+        // leftover window slots: controls of the stage's CNOTs first (a CNOT
+        // whose control is in the window is a plain register swap), then the
+        // load/store window
+        for (size_t i : taken) {
+            const TileOp& t = ops[i];
+            if (t.kind == T_XPERM && t.lctrl && !(t.lctrl & (t.lctrl - 1)) && popc(W) < r) W |= t.lctrl;
+        }
+        for (int p = b - 1; p >= 0 && popc(W) < r; p--)
+            if (natural & (1u << p)) W |= 1u << p;
+        for (int p = 0; p < b && popc(W) < r; p++) W |= 1u << p;
+        StageHdr st{};
+        int j = 0;
+        for (int p = 0; p < b; p++)
+            if (W & (1u << p)) st.w[j++] = p;
+        st.wmask = W;
+        st.op_begin = (int32_t)out.size();
+        st.n_ops = (int32_t)taken.size();
+        for (size_t i : taken) {
+            done[i] = 1;
+            TileOp t = ops[i];
+            if (t.kind == T_XPERM && t.lctrl && !(t.lctrl & (t.lctrl - 1))) t.c = __builtin_ctz(t.lctrl);
+            t.j0 = t.a >= 0 ? window_index(st, r, t.a) : -1;
+            t.j1 = t.c >= 0 ? window_index(st, r, t.c) : -1;
+            const bool two = t.kind == T_DENSE2 || t.kind == T_SWAP;
+            if (two && t.j0 > t.j1) {
+                // order the pair by window bit: swap the roles of a and c, which
+                // exchanges matrix rows/columns 1 and 2 (index bit(a) + 2 bit(c))
+                std::swap(t.a, t.c);
+                std::swap(t.j0, t.j1);
+                if (t.kind == T_DENSE2) {
+                    cd* m = &pp.mats[t.mat];
+                    cd tmp[16];
+                    const int perm[4] = {0, 2, 1, 3};
+                    for (int rr = 0; rr < 4; rr++)
+                        for (int cc = 0; cc < 4; cc++) tmp[4 * rr + cc] = m[4 * perm[rr] + perm[cc]];
+                    for (int e = 0; e < 16; e++) m[e] = tmp[e];
+                }
+            }
+            out.push_back(t);
+        }
+        pp.stages.push_back(st);
+    }
+    ops.swap(out);
+    pp.hdr.n_stages = (int32_t)pp.stages.size();
+}
+
+// ------------------------------------------------------------ fusion ---
+// Inside one block pass, one-qubit gates are folded into neighbouring
+// two-qubit gates when that saves work: a 4x4 update of a quadruple costs
+// about as much as two 2x2 updates of its pairs, so a two-qubit gate that
+// swallows the one-qubit gates before and after it on both of its qubits
+// replaces up to four pair sweeps and itself. A two-qubit gate with no
+// pending one-qubit work stays as it is (a CNOT is then a register swap, a
+// CZ a diagonal). The products are formed on the host in FP64; the result
+// equals the gate-by-gate product (Sec. III.A Eq. 5 applied in sequence).
+
+using M2 = std::array<cd, 4>;
+using M4 = std::array<cd, 16>;
+
+M2 m2_ident() { return {cd(1), cd(0), cd(0), cd(1)}; }
+
+M2 m2_mul(const M2& A, const M2& B)
+{
+    M2 r;
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) r[2 * i + j] = A[2 * i] * B[j] + A[2 * i + 1] * B[2 + j];
+    return r;
+}
+
+M4 m4_mul(const M4& A, const M4& B)
+{
+    M4 r;
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            cd t = 0;
+            for (int k = 0; k < 4; k++) t += A[4 * i + k] * B[4 * k + j];
+            r[4 * i + j] = t;
+        }
+    return r;
+}
+
+// u acting on the first (role 0) or second (role 1) qubit of a pair, in the
+// pair basis m = bit(first) + 2 bit(second).
+M4 m4_embed(const M2& u, int role)
+{
+    M4 r{};
+    for (int mo = 0; mo < 4; mo++)
+        for (int mi = 0; mi < 4; mi++) {
+            const int xo = role == 0 ? (mo & 1) : (mo >> 1), xi = role == 0 ? (mi & 1) : (mi >> 1);
+            const int yo = role == 0 ? (mo >> 1) : (mo & 1), yi = role == 0 ? (mi >> 1) : (mi & 1);
+            r[4 * mo + mi] = yo == yi ? u[2 * xo + xi] : cd(0);
+        }
+    return r;
+}
+
+// Exchange the two qubits of the basis (matrix on (q, p) -> on (p, q)).
+M4 m4_swap_roles(const M4& g)
+{
+    static const int perm[4] = {0, 2, 1, 3};
+    M4 r;
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) r[4 * i + j] = g[4 * perm[i] + perm[j]];
+    return r;
+}
+
+bool m2_is_diag(const M2& u) { return u[1] == 0.0 && u[2] == 0.0; }
+
+void fuse_ops(PlanPass& pp)
+{
+    const std::vector<TileOp> in = pp.ops;
+    std::vector<TileOp> out;
+    std::vector<M4> fused;          // matrices of fused DENSE2 ops, by out index
+    std::vector<int> fused_of;      // out index -> fused slot (-1: keep op's own matrix)
+    M2 pend[kMaxLocal];
+    bool has_pend[kMaxLocal];
+    int open[kMaxLocal];            // out index of a fused op that may absorb gates on this position
+    int role[kMaxLocal];
+    for (int p = 0; p < kMaxLocal; p++) {
+        pend[p] = m2_ident();
+        has_pend[p] = false;
+        open[p] = -1;
+        role[p] = 0;
+    }
+    auto push = [&](const TileOp& t) {
+        out.push_back(t);
+        fused_of.push_back(-1);
+    };
+    auto flush = [&](int p) {
+        if (!has_pend[p]) return;
+        const M2& u = pend[p];
+        TileOp t{};
+        t.a = p;
+        t.c = t.oa = t.oc = -1;
+        t.j0 = t.j1 = -1;
+        t.gen = GEN_NONE;
+        t.slot = -1;
+        t.mat = (int32_t)pp.mats.size();
+        if (m2_is_diag(u)) {
+            t.kind = T_DIAG;
+            pp.mats.insert(pp.mats.end(), {u[0], u[3], u[0], u[3]});
+        } else {
+            t.kind = (u[0] == 0.0 && u[1] == 1.0 && u[2] == 1.0 && u[3] == 0.0) ? T_XPERM : T_DENSE1;
+            pp.mats.insert(pp.mats.end(), u.begin(), u.end());
+        }
+        push(t);
+        has_pend[p] = false;
+        pend[p] = m2_ident();
+    };
+    auto barrier = [&](uint32_t mask) {
+        for (int p = 0; p < kMaxLocal; p++)
+            if (mask & (1u << p)) {
+                flush(p);
+                open[p] = -1;
+            }
+    };
+    auto one_qubit = [&](int p, const M2& u) {
+        if (open[p] >= 0) {
+            M4& m = fused[fused_of[open[p]]];
+            m = m4_mul(m4_embed(u, role[p]), m);
+        } else {
+            pend[p] = m2_mul(u, pend[p]);
+            has_pend[p] = true;
+        }
+    };
+    // g: matrix on (p, q) in the basis bit(p) + 2 bit(q); bare: the op to emit unfused
+    auto two_qubit = [&](int p, int q, const M4& g, const TileOp& bare, bool bare_is_dense2) {
+        if (open[p] >= 0 && open[p] == open[q]) {
+            const int idx = open[p];
+            M4& m = fused[fused_of[idx]];
+            m = m4_mul(role[p] == 0 ? g : m4_swap_roles(g), m);
+            return;
+        }
+        open[p] = open[q] = -1;
+        const bool dense_pending = (has_pend[p] && !m2_is_diag(pend[p])) || (has_pend[q] && !m2_is_diag(pend[q]));
+        if (!dense_pending && !bare_is_dense2) {
+            flush(p);
+            flush(q);
+            push(bare);
+            return;
+        }
+        M4 m = m4_mul(g, m4_mul(m4_embed(pend[p], 0), m4_embed(pend[q], 1)));
+        has_pend[p] = has_pend[q] = false;
+        pend[p] = pend[q] = m2_ident();
+        TileOp t{};
+        t.kind = T_DENSE2;
+        t.a = p;
+        t.c = q;
+        t.oa = t.oc = -1;
+        t.j0 = t.j1 = -1;
+        t.gen = GEN_NONE;
+        t.slot = -1;
+        out.push_back(t);
+        fused_of.push_back((int)fused.size());
+        fused.push_back(m);
+        open[p] = open[q] = (int)out.size() - 1;
+        role[p] = 0;
+        role[q] = 1;
+    };
+
+    for (const TileOp& t : in) {
+        const cd* mt = pp.mats.data() + t.mat;
+        const bool plain = t.lctrl == 0 && t.gctrl == 0;
+        if (t.kind == T_DENSE1 && plain) {
+            one_qubit(t.a, {mt[0], mt[1], mt[2], mt[3]});
+        } else if (t.kind == T_XPERM && plain) {
+            one_qubit(t.a, {cd(0), cd(1), cd(1), cd(0)});
+        } else if (t.kind == T_DIAG && plain && t.a >= 0 && t.c < 0 && t.oc < 0) {
+            one_qubit(t.a, {mt[0], cd(0), cd(0), mt[1]});
+        } else if (t.kind == T_DIAG && plain && t.a >= 0 && t.c >= 0) {
+            M4 g{};
+            for (int e = 0; e < 4; e++) g[5 * e] = mt[e];
+            two_qubit(t.a, t.c, g, t, false);
+        } else if (t.kind == T_XPERM && t.gctrl == 0 && t.lctrl && !(t.lctrl & (t.lctrl - 1))) {
+            // CNOT with a local control: X on a where bit c is 1, basis bit(a) + 2 bit(c)
+            const int c = __builtin_ctz(t.lctrl);
+            M4 g{};
+            g[0] = g[5] = 1.0;
+            g[4 * 2 + 3] = g[4 * 3 + 2] = 1.0;
+            two_qubit(t.a, c, g, t, false);
+        } else if ((t.kind == T_DENSE2 || t.kind == T_SWAP) && plain) {
+            M4 g{};
+            for (int e = 0; e < 16; e++) g[e] = mt[e];
+            two_qubit(t.a, t.c, g, t, t.kind == T_DENSE2);
+        } else {
+            uint32_t mask = t.lctrl;
+            if (t.a >= 0) mask |= 1u << t.a;
+            if (t.c >= 0) mask |= 1u << t.c;
+            barrier(mask);
+            push(t);
+        }
+    }
+    for (int p = 0; p < kMaxLocal; p++) flush(p);
+    for (size_t i = 0; i < out.size(); i++) {
+        if (fused_of[i] < 0) continue;
+        out[i].mat = (int32_t)pp.mats.size();
+        const M4& m = fused[fused_of[i]];
+        pp.mats.insert(pp.mats.end(), m.begin(), m.end());
+    }
+    pp.ops.swap(out);
+    pp.hdr.n_ops = (int32_t)pp.ops.size();
+}
+
+constexpr int kPhaseMinRun = 4;  // shorter runs of diagonal gates stay separate ops
+
+bool mergeable_diag(const TileOp& t, const PlanPass& pp)
+{
+    if (t.kind != T_DIAG || t.lctrl != 0 || t.gctrl != 0) return false;
+    for (int e = 0; e < 4; e++)
+        if (std::abs(std::abs(pp.mats[t.mat + e]) - 1.0) > 1e-12) return false;
+    return true;
+}
+
+uint32_t dense_positions(const TileOp& t)
+{
+    uint32_t dn, dg;
+    op_positions(t, &dn, &dg);
+    return dn;
+}
+
+uint32_t local_positions(const TileOp& t)
+{
+    uint32_t m = 0;
+    if (t.a >= 0) m |= 1u << t.a;
+    if (t.c >= 0) m |= 1u << t.c;
+    return m;
+}
+
+// Phase polynomial of a run of diagonal gates for a stage's window. A
+// diagonal d on bits (x, y) has phase angle a(x, y) = a00 + (a10 - a00) x +
+// (a01 - a00) y + (a11 - a10 - a01 + a00) x y, which is exact on {0, 1}^2;
+// the run's phase is the sum over its gates.
+TileOp make_phase(const std::vector<TileOp>& run, const StageHdr& st, int r, PlanPass& pp)
+{
+    std::map<std::array<int32_t, 5>, double> acc;
+    auto win = [&](int p) { return p < 64 ? window_index(st, r, p) : -1; };
+    auto add_lin = [&](int p, double th) {
+        const int j = win(p);
+        if (j >= 0) acc[{PH_WLIN, j, -1, -1, -1}] += th;
+        else acc[{PH_THREAD, -1, -1, p, -1}] += th;
+    };
+    auto add_quad = [&](int p, int q, double th) {
+        int jp = win(p), jq = win(q);
+        if (jp >= 0 && jq >= 0) {
+            if (jp > jq) std::swap(jp, jq);
+            acc[{PH_WQUAD, jp, jq, -1, -1}] += th;
+        } else if (jp >= 0) {
+            acc[{PH_MIXED, jp, -1, q, -1}] += th;
+        } else if (jq >= 0) {
+            acc[{PH_MIXED, jq, -1, p, -1}] += th;
+        } else {
+            acc[{PH_THREAD, -1, -1, std::min(p, q), std::max(p, q)}] += th;
+        }
+    };
+    for (const TileOp& d : run) {
+        double al[4];
+        for (int e = 0; e < 4; e++) al[e] = std::arg(pp.mats[d.mat + e]) / (2.0 * M_PI);
+        const int pa = d.a >= 0 ? d.a : 64 + d.oa;
+        const bool two = d.c >= 0 || d.oc >= 0;
+        acc[{PH_CONST, -1, -1, -1, -1}] += al[0];
+        add_lin(pa, al[1] - al[0]);
+        if (two) {
+            const int pc = d.c >= 0 ? d.c : 64 + d.oc;
+            add_lin(pc, al[2] - al[0]);
+            add_quad(pa, pc, al[3] - al[2] - al[1] + al[0]);
+        }
+    }
+    TileOp t{};
+    t.kind = T_PHASE;
+    t.a = t.c = t.oa = t.oc = -1;
+    t.j0 = t.j1 = -1;
+    t.gen = GEN_NONE;
+    t.slot = -1;
+    t.mat = (int32_t)pp.phase.size();
+    for (const auto& kv : acc) {
+        double th = kv.second - std::nearbyint(kv.second);  // angles are periodic in turns
+        if (th == 0.0) continue;
+        PhaseTerm pt{};
+        pt.kind = kv.first[0];
+        pt.j = kv.first[1];
+        pt.j2 = kv.first[2];
+        pt.p1 = kv.first[3];
+        pt.p2 = kv.first[4];
+        pt.th = th;
+        pp.phase.push_back(pt);
+    }
+    t.cnt = (int32_t)(pp.phase.size() - t.mat);
+    return t;
+}
+
+// Move each diagonal gate of a pass as late as it may go (until a later op
+// acts densely on one of its bits, or the end of the pass) so that diagonal
+// gates gather into runs, and turn each run into one phase-polynomial op.
+void merge_diagonals(PlanPass& pp, int r)
+{
+    const size_t n_st = pp.stages.size();
+    std::vector<std::vector<TileOp>> out(n_st);
+    std::vector<TileOp> pending;
+    uint32_t pending_pos = 0;
+    auto flush = [&](size_t si) {
+        if (pending.empty()) return;
+        if ((int)pending.size() >= kPhaseMinRun) out[si].push_back(make_phase(pending, pp.stages[si], r, pp));
+        else for (const TileOp& d : pending) out[si].push_back(d);
+        pending.clear();
+        pending_pos = 0;
+    };
+    for (size_t si = 0; si < n_st; si++) {
+        const StageHdr& st = pp.stages[si];
+        for (int o = 0; o < st.n_ops; o++) {
+            const TileOp& t = pp.ops[st.op_begin + o];
+            if (mergeable_diag(t, pp)) {
+                pending.push_back(t);
+                pending_pos |= local_positions(t);
+                continue;
+            }
+            if (dense_positions(t) & pending_pos) flush(si);
+            out[si].push_back(t);
+        }
+    }
+    if (n_st) flush(n_st - 1);
+    std::vector<TileOp> ops;
+    for (size_t si = 0; si < n_st; si++) {
+        pp.stages[si].op_begin = (int32_t)ops.size();
+        pp.stages[si].n_ops = (int32_t)out[si].size();
+        ops.insert(ops.end(), out[si].begin(), out[si].end());
+    }
+    pp.ops.swap(ops);
+    pp.hdr.n_ops = (int32_t)pp.ops.size();
 }
 
 }  // namespace
@@ -91,6 +559,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
         uint64_t blk_dense = 0, blk_diag = 0;
         std::vector<size_t> taken;
         int ops = 0;
+        int grads = 0;
         int scanned = 0;
         for (size_t i = first; i < items.size() && scanned < opt.lookahead; i++) {
             if (done[i]) continue;
@@ -99,12 +568,15 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
             bool ok = !(it.dense & (blk_dense | blk_diag)) && !(it.diag & blk_dense);
             if (ok) {
                 const uint64_t need = it.dense & ~S;
-                if (popc(S | need) > b || ops + it.n_ops > opt.max_ops) ok = false;
+                if (popc(S | need) > b || ops + it.n_ops > opt.max_ops ||
+                    (items[i].grad && grads >= kMaxGradPerPass))
+                    ok = false;
                 else S |= need;
             }
             if (ok) {
                 taken.push_back(i);
                 ops += it.n_ops;
+                grads += items[i].grad ? 1 : 0;
             } else {
                 blk_dense |= it.dense;
                 blk_diag |= it.diag;
@@ -174,11 +646,13 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
                 t.a = pos_of[g.q[0]];
                 t.c = -1;
                 t.oa = t.oc = -1;
+                if (is_pauli_x(g)) t.kind = T_XPERM;
                 for (int e = 0; e < 4; e++) pp.mats.push_back(g.m[e]);
             } else if (g.kind == G_DENSE2) {
                 t.a = pos_of[g.q[0]];
                 t.c = pos_of[g.q[1]];
                 t.oa = t.oc = -1;
+                if (is_swap(g)) t.kind = T_SWAP;
                 for (int e = 0; e < 16; e++) pp.mats.push_back(g.m[e]);
             } else {
                 t.a = g.q[0] >= 0 ? pos_of[g.q[0]] : -1;
@@ -190,6 +664,12 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
             pp.ops.push_back(t);
         }
         h.n_ops = (int32_t)pp.ops.size();
+        h.n_grad = grads;
+        if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
+            if (opt.fuse_gates) fuse_ops(pp);
+            plan_stages(pp, b, opt.reg_bits);
+            if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
+        }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
         passes.push_back(std::move(pp));
     }

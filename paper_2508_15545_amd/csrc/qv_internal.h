@@ -54,6 +54,10 @@ enum TileKind : int32_t {
                    // global qubit in oa / oc (bit taken from the block base),
                    // or both -1 for an absent second qubit
     T_GRAD = 3,    // Im <s1|G|s0> over the block -> partial[slot]; gen in `gen`
+    T_XPERM = 4,   // Pauli X on local target a (a swap; controls allowed)
+    T_SWAP = 5,    // exchange of local qubits a and c
+    T_PHASE = 6,   // product of diagonal gates as one phase per amplitude:
+                   // terms phase[mat .. mat + cnt) (register kernel only)
 };
 
 struct TileOp {
@@ -64,9 +68,41 @@ struct TileOp {
     int32_t gen;       // T_GRAD: GEN_X / GEN_Y / GEN_Z
     int32_t slot;      // T_GRAD: partial row
     uint64_t gctrl;    // control bits outside the block (global): block base must have them
-    int32_t mat;       // offset of the matrix in the pass matrix array (complex entries)
-    int32_t pad;
+    int32_t mat;       // offset of the matrix in the pass matrix array (complex
+                       // entries); T_PHASE: offset of its first phase term
+    int32_t j0, j1;    // register-window bits of a / c (register kernel; j0 < j1)
+    int32_t cnt;       // T_PHASE: number of phase terms
 };
+
+// One term of a phase polynomial, angles in turns (1 = 2 pi). The phase of
+// an amplitude is the sum of its terms; bit(p) is the amplitude's bit at
+// local position p (p < 64) or at global qubit p - 64 (outside the block).
+enum PhaseKind : int32_t {
+    PH_THREAD = 0,  // A += th * bit(p1) * bit(p2) (p2 < 0: linear); p1, p2 outside the window
+    PH_MIXED = 1,   // eff[j] += th * bit(p1): window bit j times a bit outside the window
+    PH_WLIN = 2,    // eff[j] += th: window bit j
+    PH_WQUAD = 3,   // qq[j][j2] += th: window bits j < j2
+    PH_CONST = 4,   // A += th
+};
+struct PhaseTerm {
+    int32_t kind;
+    int32_t j, j2;
+    int32_t p1, p2;
+    int32_t pad;
+    double th;
+};
+
+// A stage of a register-resident block pass: the amplitudes whose local
+// positions are w[0..r) are held by one thread (register bit j <-> position
+// w[j]); ops of the stage only act densely on those positions.
+constexpr int kMaxRegBits = 5;
+struct StageHdr {
+    int32_t w[kMaxRegBits];
+    uint32_t wmask;
+    int32_t n_ops;
+    int32_t op_begin;  // relative to the pass's first op
+};
+constexpr int kMaxGradPerPass = 128;
 
 constexpr int kMaxLocal = 16;
 constexpr int kMaxQubits = 34;
@@ -78,15 +114,20 @@ struct PassHdr {
     int32_t op_begin;   // first op in the op array
     int32_t local_q[kMaxLocal];   // global qubit of local position j (ascending)
     int32_t outer_q[kMaxQubits];  // global qubits not in the block (ascending)
-    int32_t pad[2];
+    int32_t n_stages;   // register kernel: stages of this pass
+    int32_t stage_begin;
+    int32_t n_grad;     // gradient reads in this pass
+    int32_t pad;
 };
 
 // One launch of a plan.
 struct PlanPass {
     enum Kind { BLOCK, SWEEP1, SWEEP2, SWEEPDIAG } kind = BLOCK;
     PassHdr hdr{};             // BLOCK
-    std::vector<TileOp> ops;   // BLOCK
+    std::vector<TileOp> ops;   // BLOCK (in stage order when stages are planned)
     std::vector<cd> mats;      // BLOCK: matrices referenced by ops
+    std::vector<StageHdr> stages;  // BLOCK, register kernel
+    std::vector<PhaseTerm> phase;  // BLOCK, register kernel: T_PHASE terms
     HostGate gate;             // SWEEP*
     double bytes = 0;          // algorithmic HBM bytes
 };
@@ -98,6 +139,9 @@ struct PlanOptions {
     int max_ops = 2048;    // ops per block pass
     int lookahead = 4096;  // gates scanned when filling a pass
     bool single_gate_sweeps = true;  // a pass holding one gate uses its sweep kernel
+    int reg_bits = 0;      // register-window bits r (0: no stage planning)
+    bool merge_diagonals = true;  // runs of diagonal gates become phase polynomials
+    bool fuse_gates = true;       // one-qubit gates fold into two-qubit 4x4 updates
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its
@@ -113,6 +157,11 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
 
 // Block size in local qubits for a state of n qubits.
 int default_block_qubits(int n, int elem_bytes, int n_states);
+
+// Register-window bits r of the register kernel (each thread holds 2^r
+// amplitudes of each state); a block of b qubits runs on it when b - r is
+// 6..9 (whole waves, at most 512 threads).
+int reg_bits_for(int elem_bytes, int n_states);
 
 // ---------------------------------------------------------- launchers ---
 
@@ -145,6 +194,12 @@ template <typename T>
 hipError_t launch_block_pass(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const TileOp* d_ops,
                              const T* d_mats, int b, double* grad_partials, int64_t grad_stride,
                              hipStream_t st);
+// Register-resident block pass (stages planned); same arguments plus the
+// stage table.
+template <typename T>
+hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const StageHdr* d_stages,
+                            const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b,
+                            double* grad_partials, int64_t grad_stride, hipStream_t st);
 template <typename T>
 hipError_t launch_pauli_expect(const T* psi, int n, const TermBatch& tb, double* partials, int n_part,
                                hipStream_t st);
