@@ -11,9 +11,18 @@ The dominant kernel's achieved bandwidth comes from HIP events around each
 of its launches (library timing on the launch stream); the CPU baseline is
 the FP64 oracle on a bounded sample of the same workload.
 
+Besides the headline value the line carries, measured in the same run:
+  sweeps       one-qubit sweep kernel bandwidth for every target qubit;
+  copy         the library's streaming copy kernel (bandwidth reference);
+  c64_vs_c128  33-qubit random U3 + CZ circuit, depth 30, in complex128 and
+               complex64 (speedup and the device-side difference);
+  adjoint      24-qubit hardware-efficient ansatz, 20 layers (960
+               parameters), complex64: forward, adjoint backward, their
+               ratio, 2 x 960 parameter-shift evaluations, gradient error
+               against the complex128 adjoint.
+
 Prints one JSON line. Flags: --gpus (only 1), --steps, --warmup, --n,
---dtype c128|c64, --no-cpu (skip the oracle leg), --extras (adjoint and
-complex64 figures, slower).
+--dtype c128|c64, --no-cpu (skip the oracle leg), --no-extras.
 """
 from __future__ import annotations
 
@@ -56,12 +65,13 @@ def run_step(st, rand, x, qft):
 
 
 def cpu_baseline(n: int, rand, seconds_budget: float = 20.0):
-    """The FP64 oracle on the first layer of the random circuit (the same
-    gates, the same 2^n-amplitude state), timed around the gate loop only."""
+    """The FP64 oracle on the first layers of the random circuit (the same
+    gates, the same 2^n-amplitude state), timed around the gate loop only,
+    stopping after the gate that crosses the time budget."""
     import oracle
 
     per_layer = n + n // 2
-    sample = rand[:per_layer]
+    sample = rand[: 4 * per_layer]
     s = oracle.basis_state(n, 0)
     t0 = time.perf_counter()
     done = 0
@@ -77,12 +87,17 @@ def cpu_baseline(n: int, rand, seconds_budget: float = 20.0):
         "unit": "gate-applications/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"first {done} gates (layer 1: U3 on every qubit + CNOT matching) of the {n}-qubit "
+        "sample": f"first {done} gates (U3 on every qubit + CNOT matching, layer by layer) of the {n}-qubit "
                   f"random circuit on a complex128 state, {dt:.1f} s",
     }
 
 
 def copy_probe(qv, B, n, dtype, elem, reps):
+    print(json.dumps({"copy_probe": copy_rate(qv, B, n, dtype, elem, reps)}), flush=True)
+    return 0
+
+
+def copy_rate(qv, B, n, dtype, elem, reps):
     """Read + write bandwidth of the library's copy kernel at the state size."""
     torch.cuda.set_device(0)
     st = qv.State(n, dtype, device="cuda:0")
@@ -97,9 +112,109 @@ def copy_probe(qv, B, n, dtype, elem, reps):
     launches, ms = st.timing_read(B.KF_COPY)
     nbytes = (1 << n) * elem
     gbs = 2.0 * nbytes * launches / (ms / 1e3) / 1e9
-    print(json.dumps({"copy_probe": {"bytes_per_launch_read": nbytes, "bytes_per_launch_write": nbytes,
-                                     "launches": launches, "avg_ms": ms / launches, "gbs": gbs}}), flush=True)
-    return 0
+    del st, src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch_read": nbytes, "bytes_per_launch_write": nbytes, "launches": launches,
+            "avg_ms": ms / launches, "gbs": gbs}
+
+
+def sweep_rates(qv, B, n, dtype, elem, reps):
+    """HBM GB/s of the one-qubit sweep kernel (unfused U3) for every target:
+    each sweep reads and writes the whole state once."""
+    torch.cuda.set_device(0)
+    st = qv.State(n, dtype, device="cuda:0").set_basis(0)
+    rng = C.rng_for(1)
+    out = {}
+    for k in range(n):
+        g = [C.gate("u3", k, params=rng.uniform(0, 2 * math.pi, 3))]
+        st.apply(g, fused=False)  # warm
+        st.timing(True)
+        st.timing_reset()
+        for _ in range(reps):
+            st.apply(g, fused=False)
+        launches, ms = st.timing_read(B.KF_SWEEP1)
+        st.timing(False)
+        out[k] = 2.0 * (1 << n) * elem / (ms / launches / 1e3) / 1e9
+    vals = list(out.values())
+    return {"gbs_by_target": out, "min_gbs": min(vals), "mean_gbs": sum(vals) / len(vals),
+            "frac_of_peak_min": min(vals) / HBM_PEAK_GBS, "frac_of_peak_mean": sum(vals) / len(vals) / HBM_PEAK_GBS}
+
+
+def timed(fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, r
+
+
+def c64_vs_c128(qv, n=33, depth=30):
+    """Random U3 + CZ matching on n qubits in both dtypes on one GPU."""
+    free = torch.cuda.mem_get_info()[0]
+    if free < (1 << n) * 24 + (8 << 30):
+        return {"skipped": f"needs {((1 << n) * 24) / 2**30:.0f} GiB free"}
+    circ = C.random_u3_layers(n, depth, seed=0, entangler="cz")
+    a = qv.State(n, torch.complex128)
+    b = qv.State(n, torch.complex64)
+    a.set_basis(0).apply(circ)
+    b.set_basis(0).apply(circ)
+    t128, _ = timed(lambda: a.set_basis(0).apply(circ))
+    t64, _ = timed(lambda: b.set_basis(0).apply(circ))
+    d = a.compare(b)
+    fid = (d["inner_re"] ** 2 + d["inner_im"] ** 2) / (d["norm2_a"] * d["norm2_b"])
+    out = {"n_qubits": n, "gates": len(circ), "depth": depth,
+           "c128_s": t128, "c64_s": t64, "speedup": t128 / t64,
+           "c128_gate_app_per_s": len(circ) / t128, "c64_gate_app_per_s": len(circ) / t64,
+           "max_abs_c64_vs_c128": d["max_abs"], "l2_c64_vs_c128": d["l2"], "fidelity": fid,
+           "passes_c128": qv.plan_stats(n, torch.complex128, circ)["n_passes"],
+           "passes_c64": qv.plan_stats(n, torch.complex64, circ)["n_passes"]}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_figures(qv, n=24, layers=20, dtype=torch.complex64, shift_evals=True):
+    """Hardware-efficient ansatz: forward (circuit + FP64 expectation),
+    adjoint backward, and the parameter-shift alternative."""
+    P = 2 * n * layers
+    th = C.hea_params(n, layers, seed=0)
+    circ = C.hea(n, layers, th)
+    H = C.zz_x_chain(n)
+    st = qv.State(n, dtype)
+    work = torch.empty_like(st.tensor)
+
+    def fwd():
+        return st.set_basis(0).apply(circ).expect(H)
+
+    fwd()
+    t_fwd, f = timed(fwd, reps=5)
+
+    def fwd_bwd():
+        st.set_basis(0).apply(circ)
+        return st.adjoint_grad(circ, H, P, work=work)
+
+    fwd_bwd()
+    t_fb, (f2, g) = timed(fwd_bwd, reps=3)
+    ref = qv.State(n, torch.complex128)
+    ref.set_basis(0).apply(circ)
+    f_ref, g_ref = ref.adjoint_grad(circ, H, P)
+    del ref
+    out = {"n_qubits": n, "layers": layers, "params": P, "gates": len(circ), "dtype": str(dtype).split(".")[-1],
+           "forward_s": t_fwd, "forward_plus_adjoint_s": t_fb,
+           "grad_over_fwd": (t_fb - t_fwd) / t_fwd, "total_over_fwd": t_fb / t_fwd,
+           "grad_max_abs_err_vs_c128": float(np.max(np.abs(g - g_ref))), "f": f, "f_err_vs_c128": abs(f - f_ref)}
+    if shift_evals:
+        def shift_all():
+            for p in range(P):
+                for sgn in (1.0, -1.0):
+                    e = th.copy()
+                    e[p] += sgn * math.pi / 2
+                    st.set_basis(0).apply(C.with_params(circ, e)).expect(H)
+        t_ps, _ = timed(shift_all)
+        out["param_shift_2P_s"] = t_ps
+        out["param_shift_over_adjoint"] = t_ps / t_fb
+    return out
 
 
 def main() -> int:
@@ -110,9 +225,11 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=29)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time the library's streaming copy kernel on two state-sized buffers")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="only time one unfused U3 sweep per target qubit (the one-qubit sweep kernel)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -128,6 +245,9 @@ def main() -> int:
     elem = 16 if args.dtype == "c128" else 8
     if args.copy_probe:
         return copy_probe(qv, B, n, dtype, elem, args.steps)
+    if args.sweeps:
+        print(json.dumps({"sweeps": sweep_rates(qv, B, n, dtype, elem, args.steps)}), flush=True)
+        return 0
     rand, x, qft = workload(n)
     gates_per_step = len(rand) + len(qft)
     plan_r = qv.plan_stats(n, dtype, rand)
@@ -207,6 +327,21 @@ def main() -> int:
         "kernel_ms": {k: v[1] for k, v in kt.items()},
         "norm_error": max(abs(a - 1) for pair in norms for a in pair),
     }
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("sweeps ...")
+        sw = sweep_rates(qv, B, n, dtype, elem, 3)
+        out["sweeps"] = {"min_gbs": sw["min_gbs"], "mean_gbs": sw["mean_gbs"],
+                         "frac_of_peak_min": sw["frac_of_peak_min"], "frac_of_peak_mean": sw["frac_of_peak_mean"],
+                         "gbs_by_target": {k: round(v) for k, v in sw["gbs_by_target"].items()}}
+        log("copy ...")
+        out["copy"] = copy_rate(qv, B, n, dtype, elem, 5)
+        out["sweeps"]["frac_of_copy_mean"] = sw["mean_gbs"] / out["copy"]["gbs"]
+        log("c64 vs c128 (33 qubits) ...")
+        out["c64_vs_c128"] = c64_vs_c128(qv)
+        log("adjoint (24-qubit ansatz) ...")
+        out["adjoint"] = adjoint_figures(qv)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, rand)

@@ -386,8 +386,8 @@ sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1
                 LaunchTimer tm(s, n_states == 2 ? KF_ADJ_BLOCK : KF_BLOCK);
                 const PassHdr* h = d_hdr + off.hdr[ih] / sizeof(PassHdr);
                 if (!pp.stages.empty()) {
-                    HIP_TRY((launch_block_reg<T>(s0, s1, s->n, n_states, h, d_stages, d_ops, d_mats, d_phase, b,
-                                                 s->d_part, nblocks, s->stream)));
+                    HIP_TRY((launch_block_reg<T>(s0, s1, s->n, n_states, pp.reg_bits, h, d_stages, d_ops, d_mats,
+                                                 d_phase, b, s->d_part, nblocks, s->stream)));
                 } else {
                     HIP_TRY((launch_block_pass<T>(s0, s1, s->n, n_states, h, d_ops, d_mats, b, s->d_part, nblocks,
                                                   s->stream)));
@@ -437,6 +437,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     const char* env = std::getenv("QVEC_BLOCK_KERNEL");
     const bool reg = g_reg_kernel && !(env && std::strcmp(env, "lds") == 0);
     o.reg_bits = reg ? reg_bits_for((int)elem, n_states) : 0;
+    const char* rb = std::getenv("QVEC_REG_BITS");  // register-window width override (3 or 4)
+    if (reg && rb && (std::strcmp(rb, "3") == 0 || std::strcmp(rb, "4") == 0)) o.reg_bits = rb[0] - '0';
     const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given inside a pass
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     return o;

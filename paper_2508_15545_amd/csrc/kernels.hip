@@ -75,17 +75,71 @@ __global__ __launch_bounds__(kThreads) void k_sweep1(T* __restrict__ psi, uint64
     }
 }
 
+// Low targets without controls (2^k < 32): every lane loads one amplitude,
+// so each wave reads and writes whole contiguous runs, and takes the
+// partner amplitude i ^ 2^k from lane (lane ^ 2^k) of the same wave. Each
+// lane computes its own output row of Eq. 5.
+template <typename T>
+__device__ __forceinline__ T shfl_xor_amp(T v, int m)
+{
+    T r;
+    if constexpr (sizeof(T) == 16) {
+        r.x = __shfl_xor(v.x, m, 64);
+        r.y = __shfl_xor(v.y, m, 64);
+    } else {
+        r.x = __shfl_xor(v.x, m, 64);
+        r.y = __shfl_xor(v.y, m, 64);
+    }
+    return r;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_sweep1_lane(T* __restrict__ psi, uint64_t N, int k, T u00, T u01,
+                                                          T u10, T u11)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const int m = 1 << k;
+    const bool hi = (threadIdx.x & m) != 0;  // bit k of the index (kThreads is a multiple of 2^k)
+    // row of Eq. 5 this lane produces: own amplitude x, partner y
+    const T a_own = hi ? u11 : u00, a_par = hi ? u10 : u01;
+    T v[P];
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t i = base + (uint64_t)r * kThreads;
+        if (i < N) v[r] = ld_nt(psi + i);
+    }
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t i = base + (uint64_t)r * kThreads;
+        const T y = shfl_xor_amp(v[r], m);  // every lane takes part in the shuffle
+        if (i < N) st_nt(psi + i, cmul2(a_own, v[r], a_par, y));
+    }
+}
+
 template <typename T>
 hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
 {
-    constexpr int P = 4;
+    // Measured on MI355X at 29 qubits: 2 pairs per thread is fastest while
+    // the partner stride is small, 4 once it is large.
     const int k = g.q[0];
     const uint64_t mask = g.ctrl | (1ull << k);
     const Ins ins = make_ins(mask);
     const uint64_t npairs = 1ull << (n - ins.cnt);
-    hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
-                       npairs, k, ins, g.ctrl, to_dev<T>(g.m[0]), to_dev<T>(g.m[1]), to_dev<T>(g.m[2]),
-                       to_dev<T>(g.m[3]));
+    const T u00 = to_dev<T>(g.m[0]), u01 = to_dev<T>(g.m[1]), u10 = to_dev<T>(g.m[2]), u11 = to_dev<T>(g.m[3]);
+    if (g.ctrl == 0 && k < 3 && n >= 8) {
+        constexpr int P = 4;
+        const uint64_t N = 1ull << n;
+        hipLaunchKernelGGL((k_sweep1_lane<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi, N, k,
+                           u00, u01, u10, u11);
+    } else if (k < 16) {
+        constexpr int P = 2;
+        hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
+                           npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+    } else {
+        constexpr int P = 4;
+        hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
+                           npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+    }
     return hipGetLastError();
 }
 
@@ -695,7 +749,7 @@ __global__ __launch_bounds__(kThreads) void k_copy(d2* __restrict__ dst, const d
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 {
-    constexpr int P = 8;
+    constexpr int P = 4;  // fastest of 4/8/16 on MI355X
     const uint64_t n16 = bytes / 16;
     hipLaunchKernelGGL((k_copy<P>), dim3(grid_for(n16, kThreads * P)), dim3(kThreads), 0, st,
                        reinterpret_cast<d2*>(dst), reinterpret_cast<const d2*>(src), n16);

@@ -122,8 +122,21 @@ __device__ __forceinline__ void reg_dense1(T (&v)[NS][1 << RB], T u00, T u01, T 
     }
 }
 
+// Register permutations (X, CNOT, SWAP) multiply by `one` (always 1.0,
+// exact) so that they are computed into the registers they overwrite: a
+// plain move would be compiled as a renaming, and every path through the op
+// loop would then have to copy the whole state back into place.
+template <typename T>
+__device__ __forceinline__ T keep(T x, typename RealOf<T>::type one)
+{
+    T r;
+    r.x = x.x * one;
+    r.y = x.y * one;
+    return r;
+}
+
 template <typename T, int RB, int NS, int J, bool CTRL>
-__device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm)
+__device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type one)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
@@ -137,8 +150,8 @@ __device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm)
                 v[s][k] = on ? y : x;
                 v[s][k1] = on ? x : y;
             } else {
-                v[s][k] = y;
-                v[s][k1] = x;
+                v[s][k] = keep(y, one);
+                v[s][k1] = keep(x, one);
             }
         }
     }
@@ -147,7 +160,7 @@ __device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm)
 // CNOT with target window bit JT and control window bit JC: swap the
 // register pairs whose control bit is set.
 template <typename T, int RB, int NS, int JT, int JC>
-__device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB])
+__device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB], typename RealOf<T>::type one)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
@@ -155,15 +168,15 @@ __device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB])
         const int k1 = k | (1 << JT);
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            const T x = v[s][k];
-            v[s][k] = v[s][k1];
-            v[s][k1] = x;
+            const T x = v[s][k], y = v[s][k1];
+            v[s][k] = keep(y, one);
+            v[s][k1] = keep(x, one);
         }
     }
 }
 
-template <typename T, int RB, int NS, int J0, int J1>
-__device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restrict__ m, uint32_t cm, bool ctrl)
+template <typename T, int RB, int NS, int J0, int J1, bool CTRL>
+__device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restrict__ m, uint32_t cm)
 {
     T u[16];
 #pragma unroll
@@ -172,7 +185,7 @@ __device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restr
     for (int k = 0; k < (1 << RB); k++) {
         if (k & ((1 << J0) | (1 << J1))) continue;
         const int idx[4] = {k, k | (1 << J0), k | (1 << J1), k | (1 << J0) | (1 << J1)};
-        const bool on = !ctrl || ((cm >> k) & 1u);
+        const bool on = !CTRL || ((cm >> k) & 1u);
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             T x[4], w[4];
@@ -186,24 +199,29 @@ __device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restr
                 w[r].y += t.y;
             }
 #pragma unroll
-            for (int e = 0; e < 4; e++) v[s][idx[e]] = on ? w[e] : x[e];
+            for (int e = 0; e < 4; e++) v[s][idx[e]] = CTRL ? (on ? w[e] : x[e]) : w[e];
         }
     }
 }
 
-template <typename T, int RB, int NS, int J0, int J1>
-__device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, bool ctrl)
+template <typename T, int RB, int NS, int J0, int J1, bool CTRL>
+__device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type one)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
         if (k & ((1 << J0) | (1 << J1))) continue;
         const int a = k | (1 << J0), c = k | (1 << J1);
-        const bool on = !ctrl || ((cm >> k) & 1u);
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             const T x = v[s][a], y = v[s][c];
-            v[s][a] = on ? y : x;
-            v[s][c] = on ? x : y;
+            if (CTRL) {
+                const bool on = (cm >> k) & 1u;
+                v[s][a] = on ? y : x;
+                v[s][c] = on ? x : y;
+            } else {
+                v[s][a] = keep(y, one);
+                v[s][c] = keep(x, one);
+            }
         }
     }
 }
@@ -234,8 +252,14 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], int gen)
     case 3: if constexpr (RB > 3) { F(3); } break;       \
     case 4: if constexpr (RB > 4) { F(4); } break;
 
+// Occupancy target per SIMD: the narrow single-state variant is held to
+// 128 VGPRs so that two 512-thread workgroups (LDS-limited) fill a CU.
+template <int RB, int NS>
+constexpr int block_waves_per_eu() { return (RB == 3 && NS == 1) ? 4 : 1; }
+
 template <typename T, int RB, int NS>
-__global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<RB, NS>())))
+void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                                                    const PassHdr* __restrict__ hdr,
                                                    const StageHdr* __restrict__ stages,
                                                    const TileOp* __restrict__ ops, const T* __restrict__ mats,
@@ -250,6 +274,8 @@ __global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __rest
     const int b = hdr->b;
     const int nloc = 1 << b;
     const int tb = b - RB;
+    // 1.0, read at run time so that the compiler keeps the multiplications
+    const typename RealOf<T>::type one = (typename RealOf<T>::type)(hdr->pad + 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const uint64_t blk = blockIdx.x;
@@ -321,7 +347,7 @@ __global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __rest
                     // control inside the window: a fixed register permutation
 #define QV_CX(A, B)                                                       \
     case A * 8 + B:                                                       \
-        if constexpr (A < RB && B < RB && A != B) reg_cx<T, RB, NS, A, B>(v); \
+        if constexpr (A < RB && B < RB && A != B) reg_cx<T, RB, NS, A, B>(v, one); \
         break;
                     switch (op.j0 * 8 + op.j1) {
                         QV_CX(0, 1) QV_CX(0, 2) QV_CX(0, 3) QV_CX(0, 4)
@@ -335,8 +361,8 @@ __global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __rest
                     break;
                 }
 #define QV_X(J)                                            \
-    if (ctrl) reg_xperm<T, RB, NS, J, true>(v, cm);        \
-    else reg_xperm<T, RB, NS, J, false>(v, cm);
+    if (ctrl) reg_xperm<T, RB, NS, J, true>(v, cm, one);   \
+    else reg_xperm<T, RB, NS, J, false>(v, cm, one);
                 switch (op.j0) { QV_J1_CASES(QV_X) }
 #undef QV_X
                 break;
@@ -349,8 +375,13 @@ __global__ __launch_bounds__(512) void k_block_reg(T* __restrict__ s0, T* __rest
 #define QV_P(A, B)                                                                     \
     case A * kMaxRegBits + B:                                                           \
         if constexpr (B < RB) {                                                         \
-            if (dense) reg_dense2<T, RB, NS, A, B>(v, m, cm, ctrl);                     \
-            else reg_swap<T, RB, NS, A, B>(v, cm, ctrl);                                \
+            if (dense) {                                                                \
+                if (ctrl) reg_dense2<T, RB, NS, A, B, true>(v, m, cm);                  \
+                else reg_dense2<T, RB, NS, A, B, false>(v, m, cm);                      \
+            } else {                                                                    \
+                if (ctrl) reg_swap<T, RB, NS, A, B, true>(v, cm, one);                  \
+                else reg_swap<T, RB, NS, A, B, false>(v, cm, one);                      \
+            }                                                                           \
         }                                                                               \
         break;
                 switch (pair) {
@@ -530,23 +561,24 @@ static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
 }
 
 template <typename T>
-hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const StageHdr* d_stages,
-                            const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
-                            int64_t gs, hipStream_t st)
+hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, int rb, const PassHdr* d_hdr,
+                            const StageHdr* d_stages, const TileOp* d_ops, const T* d_mats,
+                            const PhaseTerm* d_phase, int b, double* gp, int64_t gs, hipStream_t st)
 {
+    if (b - rb < 6 || b - rb > 9) return hipErrorInvalidValue;  // whole waves, at most 512 threads
     if (n_states == 2) {
-        constexpr int RB = sizeof(T) == 16 ? 3 : 4;
-        if (b - RB < 6 || b - RB > 9) return hipErrorInvalidValue;  // whole waves, at most 512 threads
-        return launch_reg_t<T, RB, 2>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+        if (rb == 3) return launch_reg_t<T, 3, 2>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+        if (rb == 4) return launch_reg_t<T, 4, 2>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+        return hipErrorInvalidValue;
     }
-    constexpr int RB = 4;
-    if (b - RB < 6 || b - RB > 9) return hipErrorInvalidValue;
-    return launch_reg_t<T, RB, 1>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+    if (rb == 3) return launch_reg_t<T, 3, 1>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+    if (rb == 4) return launch_reg_t<T, 4, 1>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+    return hipErrorInvalidValue;
 }
 
-template hipError_t launch_block_reg<d2>(d2*, d2*, int, int, const PassHdr*, const StageHdr*, const TileOp*,
+template hipError_t launch_block_reg<d2>(d2*, d2*, int, int, int, const PassHdr*, const StageHdr*, const TileOp*,
                                          const d2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
-template hipError_t launch_block_reg<f2>(f2*, f2*, int, int, const PassHdr*, const StageHdr*, const TileOp*,
+template hipError_t launch_block_reg<f2>(f2*, f2*, int, int, int, const PassHdr*, const StageHdr*, const TileOp*,
                                          const f2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
 
 }  // namespace qv

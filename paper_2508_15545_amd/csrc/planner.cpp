@@ -37,7 +37,7 @@ int default_block_qubits(int n, int elem_bytes, int n_states)
     return std::min(n, lb);
 }
 
-int reg_bits_for(int elem_bytes, int n_states) { return (n_states == 2 && elem_bytes == 16) ? 3 : 4; }
+int reg_bits_for(int elem_bytes, int n_states) { return n_states == 2 ? 3 : 4; }
 
 namespace {
 
@@ -668,6 +668,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
         if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
             if (opt.fuse_gates) fuse_ops(pp);
             plan_stages(pp, b, opt.reg_bits);
+            pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
         }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;

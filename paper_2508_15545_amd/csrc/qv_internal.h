@@ -128,6 +128,7 @@ struct PlanPass {
     std::vector<cd> mats;      // BLOCK: matrices referenced by ops
     std::vector<StageHdr> stages;  // BLOCK, register kernel
     std::vector<PhaseTerm> phase;  // BLOCK, register kernel: T_PHASE terms
+    int reg_bits = 0;              // BLOCK, register kernel: window bits r
     HostGate gate;             // SWEEP*
     double bytes = 0;          // algorithmic HBM bytes
 };
@@ -197,9 +198,10 @@ hipError_t launch_block_pass(T* s0, T* s1, int n, int n_states, const PassHdr* d
 // Register-resident block pass (stages planned); same arguments plus the
 // stage table.
 template <typename T>
-hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const StageHdr* d_stages,
-                            const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b,
-                            double* grad_partials, int64_t grad_stride, hipStream_t st);
+hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, int reg_bits, const PassHdr* d_hdr,
+                            const StageHdr* d_stages, const TileOp* d_ops, const T* d_mats,
+                            const PhaseTerm* d_phase, int b, double* grad_partials, int64_t grad_stride,
+                            hipStream_t st);
 template <typename T>
 hipError_t launch_pauli_expect(const T* psi, int n, const TermBatch& tb, double* partials, int n_part,
                                hipStream_t st);
