@@ -439,8 +439,23 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.reg_bits = reg ? reg_bits_for((int)elem, n_states) : 0;
     const char* rb = std::getenv("QVEC_REG_BITS");  // register-window width override (3 or 4)
     if (reg && rb && (std::strcmp(rb, "3") == 0 || std::strcmp(rb, "4") == 0)) o.reg_bits = rb[0] - '0';
-    const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given inside a pass
+    const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given (no 4x4 fusion)
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
+    o.prefuse = o.fuse_gates && o.reg_bits > 0;
+    const char* bq = std::getenv("QVEC_BLOCK_QUBITS");  // block size override (local qubits)
+    if (bq) {
+        const int v = std::atoi(bq);
+        if (v >= 1 && v <= kMaxLocal) o.b = std::min(n, v);
+    }
+    // Keep the block within what the chosen kernel can hold: the register
+    // kernel needs at most 160 KiB of LDS and at most 512 threads; the LDS
+    // kernel has a fixed 64 KiB block.
+    if (o.reg_bits > 0) {
+        while (o.b > 1 && ((size_t)n_states << o.b) * elem > (160u << 10)) o.b--;
+        while (o.b - o.reg_bits > 9) o.b--;
+    } else {
+        o.b = std::min(o.b, (elem == 16 ? 12 : 13) - (n_states == 2 ? 1 : 0));
+    }
     return o;
 }
 

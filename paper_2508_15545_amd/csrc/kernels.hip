@@ -493,6 +493,7 @@ template <typename T>
 hipError_t launch_block_pass(T* s0, T* s1, int n, int n_states, const PassHdr* d_hdr, const TileOp* d_ops,
                              const T* d_mats, int b, double* gp, int64_t gs, hipStream_t st)
 {
+    if (b > block_lb<T>(n_states)) return hipErrorInvalidValue;  // the block must fit the kernel's LDS
     if (n_states == 2)
         return launch_block_t<T, block_lb<T>(2), 2>(s0, s1, n, d_hdr, d_ops, d_mats, b, gp, gs, st);
     return launch_block_t<T, block_lb<T>(1), 1>(s0, s1, n, d_hdr, d_ops, d_mats, b, gp, gs, st);

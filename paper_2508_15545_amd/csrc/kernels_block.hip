@@ -329,72 +329,52 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         for (int o = 0; o < sh.n_ops; o++) {
             const TileOp op = po[sh.op_begin + o];
             if ((base & op.gctrl) != op.gctrl) continue;  // uniform over the block
-            const bool ctrl = op.lctrl != 0;
-            const bool cx_in_window = op.kind == T_XPERM && op.j1 >= 0 && op.c >= 0 && op.lctrl == (1u << op.c);
-            const uint32_t cm = (ctrl && !cx_in_window) ? ctrl_bits<RB>(op.lctrl, cur_tl, cur_w) : ~0u;
-            switch (op.kind) {
-            case T_DENSE1: {
-                const T u00 = mats[op.mat], u01 = mats[op.mat + 1], u10 = mats[op.mat + 2], u11 = mats[op.mat + 3];
-#define QV_D1(J)                                                                      \
-    if (ctrl) reg_dense1<T, RB, NS, J, true>(v, u00, u01, u10, u11, cm);              \
-    else reg_dense1<T, RB, NS, J, false>(v, u00, u01, u10, u11, cm);
-                switch (op.j0) { QV_J1_CASES(QV_D1) }
-#undef QV_D1
-                break;
-            }
-            case T_XPERM: {
-                if (op.j1 >= 0 && op.c >= 0 && op.lctrl == (1u << op.c)) {
-                    // control inside the window: a fixed register permutation
-#define QV_CX(A, B)                                                       \
-    case A * 8 + B:                                                       \
-        if constexpr (A < RB && B < RB && A != B) reg_cx<T, RB, NS, A, B>(v, one); \
+            const int code = op.code;
+            const uint32_t cm = (code >= RC_D1C && code < RC_D1C + 5) || (code >= RC_XC && code < RC_XC + 5) ||
+                                        (code >= RC_D2C && code < RC_SW) || (code >= RC_SWC && code < RC_DIAG) ||
+                                        (code == RC_DIAG && op.lctrl)
+                                    ? ctrl_bits<RB>(op.lctrl, cur_tl, cur_w)
+                                    : ~0u;
+            switch (code) {
+#define QV_C1(BASE, J, STMT) \
+    case BASE + J:           \
+        if constexpr (J < RB) { STMT; } \
         break;
-                    switch (op.j0 * 8 + op.j1) {
-                        QV_CX(0, 1) QV_CX(0, 2) QV_CX(0, 3) QV_CX(0, 4)
-                        QV_CX(1, 0) QV_CX(1, 2) QV_CX(1, 3) QV_CX(1, 4)
-                        QV_CX(2, 0) QV_CX(2, 1) QV_CX(2, 3) QV_CX(2, 4)
-                        QV_CX(3, 0) QV_CX(3, 1) QV_CX(3, 2) QV_CX(3, 4)
-                        QV_CX(4, 0) QV_CX(4, 1) QV_CX(4, 2) QV_CX(4, 3)
-                    default: break;
-                    }
-#undef QV_CX
-                    break;
-                }
-#define QV_X(J)                                            \
-    if (ctrl) reg_xperm<T, RB, NS, J, true>(v, cm, one);   \
-    else reg_xperm<T, RB, NS, J, false>(v, cm, one);
-                switch (op.j0) { QV_J1_CASES(QV_X) }
-#undef QV_X
-                break;
-            }
-            case T_DENSE2:
-            case T_SWAP: {
-                const int pair = op.j0 * kMaxRegBits + op.j1;
-                const bool dense = op.kind == T_DENSE2;
-                const T* m = mats + op.mat;
-#define QV_P(A, B)                                                                     \
-    case A * kMaxRegBits + B:                                                           \
-        if constexpr (B < RB) {                                                         \
-            if (dense) {                                                                \
-                if (ctrl) reg_dense2<T, RB, NS, A, B, true>(v, m, cm);                  \
-                else reg_dense2<T, RB, NS, A, B, false>(v, m, cm);                      \
-            } else {                                                                    \
-                if (ctrl) reg_swap<T, RB, NS, A, B, true>(v, cm, one);                  \
-                else reg_swap<T, RB, NS, A, B, false>(v, cm, one);                      \
-            }                                                                           \
-        }                                                                               \
+#define QV_ALL1(BASE, F) QV_C1(BASE, 0, F(0)) QV_C1(BASE, 1, F(1)) QV_C1(BASE, 2, F(2)) QV_C1(BASE, 3, F(3)) QV_C1(BASE, 4, F(4))
+#define QV_C2(BASE, A, B, F) \
+    case BASE + 5 * A + B:   \
+        if constexpr (A < RB && B < RB && A != B) { F(A, B); } \
         break;
-                switch (pair) {
-                    QV_P(0, 1) QV_P(0, 2) QV_P(0, 3) QV_P(0, 4) QV_P(1, 2)
-                    QV_P(1, 3) QV_P(1, 4) QV_P(2, 3) QV_P(2, 4) QV_P(3, 4)
-                default: break;
-                }
-#undef QV_P
-                break;
-            }
-            case T_DIAG: {
+#define QV_PAIRS(BASE, F) \
+    QV_C2(BASE, 0, 1, F) QV_C2(BASE, 0, 2, F) QV_C2(BASE, 0, 3, F) QV_C2(BASE, 0, 4, F) QV_C2(BASE, 1, 2, F) \
+    QV_C2(BASE, 1, 3, F) QV_C2(BASE, 1, 4, F) QV_C2(BASE, 2, 3, F) QV_C2(BASE, 2, 4, F) QV_C2(BASE, 3, 4, F)
+#define QV_ORDERED(BASE, F) \
+    QV_PAIRS(BASE, F) \
+    QV_C2(BASE, 1, 0, F) QV_C2(BASE, 2, 0, F) QV_C2(BASE, 3, 0, F) QV_C2(BASE, 4, 0, F) QV_C2(BASE, 2, 1, F) \
+    QV_C2(BASE, 3, 1, F) QV_C2(BASE, 4, 1, F) QV_C2(BASE, 3, 2, F) QV_C2(BASE, 4, 2, F) QV_C2(BASE, 4, 3, F)
+#define QV_M2 mats[op.mat], mats[op.mat + 1], mats[op.mat + 2], mats[op.mat + 3]
+#define F_D1(J) reg_dense1<T, RB, NS, J, false>(v, QV_M2, cm)
+#define F_D1C(J) reg_dense1<T, RB, NS, J, true>(v, QV_M2, cm)
+#define F_X(J) reg_xperm<T, RB, NS, J, false>(v, cm, one)
+#define F_XC(J) reg_xperm<T, RB, NS, J, true>(v, cm, one)
+#define F_CX(A, B) reg_cx<T, RB, NS, A, B>(v, one)
+#define F_D2(A, B) reg_dense2<T, RB, NS, A, B, false>(v, mats + op.mat, cm)
+#define F_D2C(A, B) reg_dense2<T, RB, NS, A, B, true>(v, mats + op.mat, cm)
+#define F_SW(A, B) reg_swap<T, RB, NS, A, B, false>(v, cm, one)
+#define F_SWC(A, B) reg_swap<T, RB, NS, A, B, true>(v, cm, one)
+                QV_ALL1(RC_D1, F_D1)
+                QV_ALL1(RC_D1C, F_D1C)
+                QV_ALL1(RC_X, F_X)
+                QV_ALL1(RC_XC, F_XC)
+                QV_ORDERED(RC_CX, F_CX)
+                QV_PAIRS(RC_D2, F_D2)
+                QV_PAIRS(RC_D2C, F_D2C)
+                QV_PAIRS(RC_SW, F_SW)
+                QV_PAIRS(RC_SWC, F_SWC)
+            case RC_DIAG: {
                 const T d0 = mats[op.mat], d1 = mats[op.mat + 1], dd2 = mats[op.mat + 2], d3 = mats[op.mat + 3];
                 const int a = op.a, c = op.c;
+                const bool ctrl = op.lctrl != 0;
                 const int ua = a < 0 ? (op.oa >= 0 ? (int)((base >> op.oa) & 1) : 0) : 0;
                 const int uc = c < 0 ? (op.oc >= 0 ? (int)((base >> op.oc) & 1) : 0) : 0;
 #pragma unroll
@@ -414,7 +394,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 }
                 break;
             }
-            case T_PHASE: {
+            case RC_PHASE: {
                 // A: the part of the angle fixed for this thread; eff[j] and
                 // qq[j][j2]: coefficients of window bits j and j & j2.
                 double A = 0, eff[RB], qq[RB][RB];
@@ -482,30 +462,47 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 }
                 break;
             }
-            case T_GRAD: {
+            case RC_GZ: {
                 if constexpr (NS == 2) {
                     double acc = 0;
-                    if (op.gen == GEN_Z) {
-                        const int a = op.a;
-                        const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
+                    const int a = op.a;
+                    const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
 #pragma unroll
-                        for (int k = 0; k < R; k++) {
-                            const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
-                            const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
-                            const T f = v[0][k], m = v[1][k];
-                            const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
-                            acc += bit ? -im : im;
-                        }
-                    } else {
-#define QV_G(J) acc = reg_grad_xy<T, RB, J>(v, op.gen);
-                        switch (op.j0) { QV_J1_CASES(QV_G) }
-#undef QV_G
+                    for (int k = 0; k < R; k++) {
+                        const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
+                        const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
+                        const T f = v[0][k], m = v[1][k];
+                        const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+                        acc += bit ? -im : im;
                     }
                     acc = wave_sum(acc);
                     if (lane == 0) red[op.slot * 8 + wave] = acc;
                 }
                 break;
             }
+#define F_G(J)                                                   \
+    if constexpr (NS == 2) {                                     \
+        double acc = reg_grad_xy<T, RB, J>(v, op.gen);           \
+        acc = wave_sum(acc);                                     \
+        if (lane == 0) red[op.slot * 8 + wave] = acc;            \
+    }
+                QV_ALL1(RC_GXY, F_G)
+#undef F_G
+#undef F_D1
+#undef F_D1C
+#undef F_X
+#undef F_XC
+#undef F_CX
+#undef F_D2
+#undef F_D2C
+#undef F_SW
+#undef F_SWC
+#undef QV_M2
+#undef QV_ORDERED
+#undef QV_PAIRS
+#undef QV_C2
+#undef QV_ALL1
+#undef QV_C1
             default: break;
             }
         }

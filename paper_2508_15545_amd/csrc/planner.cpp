@@ -31,9 +31,11 @@ namespace qv {
 
 int default_block_qubits(int n, int elem_bytes, int n_states)
 {
-    // 64 KiB of LDS per workgroup: 4096 complex128 / 8192 complex64
-    // amplitudes, halved when two states share the block.
-    const int lb = (elem_bytes == 16 ? 12 : 13) - (n_states == 2 ? 1 : 0);
+    // 64 KiB of LDS per workgroup (4096 complex128 / 8192 complex64
+    // amplitudes, halved when the adjoint carries two states): two
+    // workgroups share a CU. Measured on MI355X, this beats one 128 KiB
+    // workgroup per CU even though the larger block needs fewer passes.
+    const int lb = n_states == 2 ? (elem_bytes == 16 ? 11 : 12) : (elem_bytes == 16 ? 12 : 13);
     return std::min(n, lb);
 }
 
@@ -46,12 +48,15 @@ int popc(uint64_t v) { return __builtin_popcountll(v); }
 struct ItemBits {
     uint64_t dense;  // qubits acted on non-diagonally (must be local)
     uint64_t diag;   // qubits acted on diagonally (may be outside the block)
+    uint64_t want;   // qubits that need not be local but let the gate fuse when they are
     int n_ops;
 };
 
 ItemBits bits_of(const PlanItem& it)
 {
-    ItemBits b{dense_bits(it.g), diag_bits(it.g), 1};
+    ItemBits b{dense_bits(it.g), diag_bits(it.g), 0, 1};
+    if (it.g.kind == G_DENSE1 && it.g.ctrl && !(it.g.ctrl & (it.g.ctrl - 1))) b.want = it.g.ctrl;
+    if (it.g.kind == G_DIAG && it.g.q[1] >= 0 && !it.g.ctrl) b.want = (1ull << it.g.q[0]) | (1ull << it.g.q[1]);
     if (it.grad) {
         b.n_ops++;
         if (it.g.gen == GEN_Z) b.diag |= 1ull << it.g.q[0];
@@ -205,6 +210,30 @@ void plan_stages(PlanPass& pp, int b, int r)
     }
     ops.swap(out);
     pp.hdr.n_stages = (int32_t)pp.stages.size();
+}
+
+// Flat dispatch code of an op for the register kernel (after stages and
+// diagonal merging).
+int32_t reg_code(const TileOp& t)
+{
+    const bool ctrl = t.lctrl != 0;
+    switch (t.kind) {
+    case T_DENSE1: return (ctrl ? RC_D1C : RC_D1) + t.j0;
+    case T_XPERM:
+        if (t.j1 >= 0 && t.c >= 0 && t.lctrl == (1u << t.c)) return RC_CX + 5 * t.j0 + t.j1;
+        return (ctrl ? RC_XC : RC_X) + t.j0;
+    case T_DENSE2: return (ctrl ? RC_D2C : RC_D2) + 5 * t.j0 + t.j1;
+    case T_SWAP: return (ctrl ? RC_SWC : RC_SW) + 5 * t.j0 + t.j1;
+    case T_DIAG: return RC_DIAG;
+    case T_PHASE: return RC_PHASE;
+    case T_GRAD: return t.gen == GEN_Z ? RC_GZ : RC_GXY + t.j0;
+    default: return RC_NONE;
+    }
+}
+
+void set_reg_codes(PlanPass& pp)
+{
+    for (TileOp& t : pp.ops) t.code = reg_code(t);
 }
 
 // ------------------------------------------------------------ fusion ---
@@ -403,6 +432,120 @@ void fuse_ops(PlanPass& pp)
     pp.hdr.n_ops = (int32_t)pp.ops.size();
 }
 
+// Whole-circuit version of the same fusion, on global qubits, before the
+// passes are formed: a two-qubit gate with one-qubit work pending on its
+// qubits becomes a 4x4 that also takes the one-qubit gates that follow it
+// (until another gate touches the qubit). In layered circuits this makes
+// every other layer of two-qubit gates absorb the one-qubit gates on both
+// sides, and leaves the layers in between as plain CNOTs / CZs.
+std::vector<HostGate> prefuse_gates(const std::vector<HostGate>& in)
+{
+    std::vector<HostGate> out;
+    std::vector<int> open(kMaxQubits + 1, -1), role(kMaxQubits + 1, 0);
+    std::vector<M2> pend(kMaxQubits + 1, m2_ident());
+    std::vector<char> has_pend(kMaxQubits + 1, 0);
+    auto emit_pending = [&](int q) {
+        if (!has_pend[q]) return;
+        HostGate g;
+        const M2& u = pend[q];
+        g.q[0] = q;
+        if (m2_is_diag(u)) {
+            g.kind = G_DIAG;
+            g.m[0] = u[0];
+            g.m[1] = u[3];
+            g.m[2] = u[0];
+            g.m[3] = u[3];
+        } else {
+            g.kind = G_DENSE1;
+            for (int e = 0; e < 4; e++) g.m[e] = u[e];
+        }
+        out.push_back(g);
+        has_pend[q] = 0;
+        pend[q] = m2_ident();
+    };
+    auto barrier = [&](uint64_t mask) {
+        for (int q = 0; q < kMaxQubits; q++)
+            if (mask & (1ull << q)) {
+                emit_pending(q);
+                open[q] = -1;
+            }
+    };
+    auto m4_of = [&](int idx) {
+        M4 m;
+        for (int e = 0; e < 16; e++) m[e] = out[idx].m[e];
+        return m;
+    };
+    auto set_m4 = [&](int idx, const M4& m) {
+        for (int e = 0; e < 16; e++) out[idx].m[e] = m[e];
+    };
+    for (const HostGate& g : in) {
+        const bool one_q = (g.kind == G_DENSE1 && !g.ctrl) || (g.kind == G_DIAG && !g.ctrl && g.q[1] < 0);
+        if (one_q) {
+            const int q = g.q[0];
+            const M2 u = g.kind == G_DENSE1 ? M2{g.m[0], g.m[1], g.m[2], g.m[3]} : M2{g.m[0], cd(0), cd(0), g.m[1]};
+            if (open[q] >= 0) {
+                set_m4(open[q], m4_mul(m4_embed(u, role[q]), m4_of(open[q])));
+            } else {
+                pend[q] = m2_mul(u, pend[q]);
+                has_pend[q] = 1;
+            }
+            continue;
+        }
+        // two-qubit forms: CNOT (one control), CZ/CP (two-qubit diagonal), 4x4
+        int p = -1, q = -1;
+        M4 gm{};
+        if (g.kind == G_DENSE1 && g.ctrl && !(g.ctrl & (g.ctrl - 1))) {
+            p = g.q[0];
+            q = __builtin_ctzll(g.ctrl);
+            // X (or any 2x2) on p where bit q is 1, basis bit(p) + 2 bit(q)
+            gm[0] = gm[5] = 1.0;
+            gm[4 * 2 + 2] = g.m[0];
+            gm[4 * 2 + 3] = g.m[1];
+            gm[4 * 3 + 2] = g.m[2];
+            gm[4 * 3 + 3] = g.m[3];
+        } else if (g.kind == G_DIAG && !g.ctrl && g.q[1] >= 0) {
+            p = g.q[0];
+            q = g.q[1];
+            for (int e = 0; e < 4; e++) gm[5 * e] = g.m[e];
+        } else if (g.kind == G_DENSE2 && !g.ctrl) {
+            p = g.q[0];
+            q = g.q[1];
+            for (int e = 0; e < 16; e++) gm[e] = g.m[e];
+        } else {
+            barrier(dense_bits(g) | diag_bits(g));
+            out.push_back(g);
+            continue;
+        }
+        if (open[p] >= 0 && open[p] == open[q]) {
+            const int idx = open[p];
+            set_m4(idx, m4_mul(role[p] == 0 ? gm : m4_swap_roles(gm), m4_of(idx)));
+            continue;
+        }
+        open[p] = open[q] = -1;
+        const bool dense_pending = (has_pend[p] && !m2_is_diag(pend[p])) || (has_pend[q] && !m2_is_diag(pend[q]));
+        if (!dense_pending && g.kind != G_DENSE2) {
+            emit_pending(p);
+            emit_pending(q);
+            out.push_back(g);
+            continue;
+        }
+        const M4 m = m4_mul(gm, m4_mul(m4_embed(pend[p], 0), m4_embed(pend[q], 1)));
+        has_pend[p] = has_pend[q] = 0;
+        pend[p] = pend[q] = m2_ident();
+        HostGate f;
+        f.kind = G_DENSE2;
+        f.q[0] = p;
+        f.q[1] = q;
+        for (int e = 0; e < 16; e++) f.m[e] = m[e];
+        out.push_back(f);
+        open[p] = open[q] = (int)out.size() - 1;
+        role[p] = 0;
+        role[q] = 1;
+    }
+    for (int q = 0; q < kMaxQubits; q++) emit_pending(q);
+    return out;
+}
+
 constexpr int kPhaseMinRun = 4;  // shorter runs of diagonal gates stay separate ops
 
 bool mergeable_diag(const TileOp& t, const PlanPass& pp)
@@ -532,7 +675,7 @@ void merge_diagonals(PlanPass& pp, int r)
 
 }  // namespace
 
-std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, const PlanOptions& opt, int elem)
+std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in, const PlanOptions& opt, int elem)
 {
     if (n < 1 || n > kMaxQubits) throw std::runtime_error("qubit count out of range");
     const int b = std::min(opt.b, n);
@@ -540,6 +683,24 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
     const uint64_t all = (n == 64) ? ~0ull : ((1ull << n) - 1);
     const int n_states = opt.n_states;
 
+    std::vector<PlanItem> fused_items;
+    const std::vector<PlanItem>* src = &items_in;
+    if (opt.prefuse) {
+        bool any_grad = false;
+        for (const PlanItem& it : items_in) any_grad |= it.grad;
+        if (!any_grad) {
+            std::vector<HostGate> gs;
+            gs.reserve(items_in.size());
+            for (const PlanItem& it : items_in) gs.push_back(it.g);
+            for (const HostGate& g : prefuse_gates(gs)) {
+                PlanItem it;
+                it.g = g;
+                fused_items.push_back(it);
+            }
+            src = &fused_items;
+        }
+    }
+    const std::vector<PlanItem>& items = *src;
     std::vector<ItemBits> ib(items.size());
     for (size_t i = 0; i < items.size(); i++) ib[i] = bits_of(items[i]);
 
@@ -572,6 +733,10 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
                     (items[i].grad && grads >= kMaxGradPerPass))
                     ok = false;
                 else S |= need;
+                if (ok && opt.want_local) {
+                    const uint64_t w = it.want & ~S;
+                    if (w && popc(S | w) <= b - opt.want_reserve) S |= w;
+                }
             }
             if (ok) {
                 taken.push_back(i);
@@ -670,6 +835,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, co
             plan_stages(pp, b, opt.reg_bits);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
+            set_reg_codes(pp);
         }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
         passes.push_back(std::move(pp));

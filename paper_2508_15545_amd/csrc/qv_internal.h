@@ -72,6 +72,27 @@ struct TileOp {
                        // entries); T_PHASE: offset of its first phase term
     int32_t j0, j1;    // register-window bits of a / c (register kernel; j0 < j1)
     int32_t cnt;       // T_PHASE: number of phase terms
+    int32_t code;      // register kernel: flat dispatch code (RegCode)
+    int32_t pad2;
+};
+
+// Flat dispatch codes of the register kernel: one switch case per op kind,
+// window bits and control flavour, so that every op has one merge point.
+enum RegCode : int32_t {
+    RC_NONE = 0,
+    RC_D1 = 1,      // + j0: dense 2x2 on window bit j0
+    RC_D1C = 8,     // + j0: the same with local controls
+    RC_X = 16,      // + j0: Pauli X (register swap)
+    RC_XC = 24,     // + j0: X with local controls outside the window
+    RC_CX = 32,     // + 5 jt + jc: X on jt controlled by window bit jc
+    RC_D2 = 64,     // + 5 j0 + j1: dense 4x4 on window bits j0 < j1
+    RC_D2C = 96,    // + 5 j0 + j1: the same with local controls
+    RC_SW = 128,    // + 5 j0 + j1: SWAP
+    RC_SWC = 160,   // + 5 j0 + j1: controlled SWAP
+    RC_DIAG = 192,  // diagonal on any bits
+    RC_PHASE = 193, // phase polynomial
+    RC_GZ = 194,    // gradient read, G = Z
+    RC_GXY = 200,   // + j0: gradient read, G = X or Y on window bit j0
 };
 
 // One term of a phase polynomial, angles in turns (1 = 2 pi). The phase of
@@ -143,6 +164,9 @@ struct PlanOptions {
     int reg_bits = 0;      // register-window bits r (0: no stage planning)
     bool merge_diagonals = true;  // runs of diagonal gates become phase polynomials
     bool fuse_gates = true;       // one-qubit gates fold into two-qubit 4x4 updates
+    bool prefuse = false;         // fuse one-qubit gates into two-qubit gates over the whole circuit first
+    bool want_local = false;      // also bring controls / diagonal partners into a pass when there is room
+    int want_reserve = 0;         // ... keeping this many local slots free for later targets
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its
