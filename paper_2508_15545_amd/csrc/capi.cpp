@@ -442,6 +442,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given (no 4x4 fusion)
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     o.prefuse = o.fuse_gates && o.reg_bits > 0;
+    const char* wm = std::getenv("QVEC_WAVE_MODE");  // "0" | "1" | "2": see PlanOptions::wave_mode
+    if (wm && wm[0] >= '0' && wm[0] <= '2' && wm[1] == 0) o.wave_mode = wm[0] - '0';
     const char* bq = std::getenv("QVEC_BLOCK_QUBITS");  // block size override (local qubits)
     if (bq) {
         const int v = std::atoi(bq);

@@ -17,6 +17,8 @@
 // the lowest local positions, which hold the lowest qubits and so
 // contiguous runs of memory); the planner starts and, when it can, ends on
 // that window.
+#include <cstdlib>
+
 #include "device_common.h"
 
 namespace qv {
@@ -33,19 +35,22 @@ __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
     return l ^ ((h ^ (h >> e) ^ (h >> (2 * e))) & m);
 }
 
-// Local index bits contributed by the thread index when the window is W:
-// thread bit i goes to the i-th lowest position outside W.
-__device__ __forceinline__ uint32_t thread_part(uint32_t wmask, int b, int tid)
+// Local index bits contributed by the thread index: thread bit i sits at
+// local position tpos[i].
+__device__ __forceinline__ uint32_t thread_part(const int32_t* tpos, int tb, int tid)
 {
     uint32_t tl = 0;
-    int i = 0;
-    for (int p = 0; p < b; p++) {
-        if (!((wmask >> p) & 1u)) {
-            tl |= (uint32_t)((tid >> i) & 1) << p;
-            i++;
-        }
-    }
+    for (int i = 0; i < tb; i++) tl |= (uint32_t)((tid >> i) & 1) << tpos[i];
     return tl;
+}
+
+// Orders this wave's LDS writes before its later LDS reads (a wave's LDS
+// operations execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int RB>
@@ -64,7 +69,7 @@ __device__ __forceinline__ uint32_t window_part(int k, const int (&w)[kMaxRegBit
 template <typename T, int RB, int NS>
 __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, uint32_t tl_old,
                                          const int (&w_old)[kMaxRegBits], uint32_t tl_new,
-                                         const int (&w_new)[kMaxRegBits])
+                                         const int (&w_new)[kMaxRegBits], bool wave_only)
 {
     constexpr int R = 1 << RB;
     unsigned char* base = reinterpret_cast<unsigned char*>(lds);
@@ -78,7 +83,10 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
 #pragma unroll
         for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
     }
-    __syncthreads();
+    // Within-wave exchanges (the wave positions did not move) read only what
+    // the same wave wrote: no workgroup barrier.
+    if (wave_only) wave_lds_sync();
+    else __syncthreads();
 #pragma unroll
     for (int k = 0; k < R; k++) {
         const uint32_t wk = __builtin_amdgcn_readfirstlane(lds_swizzle<T>(window_part<RB>(k, w_new)) * (uint32_t)sizeof(T));
@@ -86,7 +94,8 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
 #pragma unroll
         for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
     }
-    __syncthreads();
+    if (wave_only) wave_lds_sync();
+    else __syncthreads();
 }
 
 // Control mask of an op, one bit per register: its local control bits are all set.
@@ -278,21 +287,22 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     const typename RealOf<T>::type one = (typename RealOf<T>::type)(hdr->pad + 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const uint64_t blk = blockIdx.x;
-
+    const uint64_t nblocks = 1ull << hdr->n_outer;
+    // A grid smaller than the block count walks the blocks in strides.
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     uint64_t base = 0;
     for (int j = 0; j < hdr->n_outer; j++) base |= ((blk >> j) & 1ull) << hdr->outer_q[j];
 
-    // Natural mapping: thread bits on positions 0..tb-1, registers on tb..b-1.
+    // Load/store mapping (lanes on the lowest positions, see the planner).
     int wn[kMaxRegBits];
 #pragma unroll
-    for (int j = 0; j < kMaxRegBits; j++) wn[j] = j < RB ? tb + j : 0;
-    const uint32_t natural = ((1u << RB) - 1) << tb;
+    for (int j = 0; j < kMaxRegBits; j++) wn[j] = hdr->nat.w[j];
+    const uint32_t tl_nat = thread_part(hdr->nat.tpos, tb, tid);
     uint64_t gt = base;
-    for (int j = 0; j < tb; j++) gt |= (uint64_t)((tid >> j) & 1) << hdr->local_q[j];
-    int qr[RB];  // global qubits of the natural window
+    for (int i = 0; i < tb; i++) gt |= (uint64_t)((tid >> i) & 1) << hdr->local_q[hdr->nat.tpos[i]];
+    int qr[RB];  // global qubits of the load window
 #pragma unroll
-    for (int j = 0; j < RB; j++) qr[j] = hdr->local_q[tb + j];
+    for (int j = 0; j < RB; j++) qr[j] = hdr->local_q[wn[j]];
 
     T v[NS][R];
 #pragma unroll
@@ -305,23 +315,21 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         if (NS == 2) v[NS - 1][k] = ld_nt(s1 + g);
     }
 
-    uint32_t cur_mask = natural;
     int cur_w[kMaxRegBits];
 #pragma unroll
     for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = wn[j];
-    uint32_t cur_tl = tid;  // natural: thread bits are the low positions
+    uint32_t cur_tl = tl_nat;
 
     const TileOp* po = ops + hdr->op_begin;
     const int n_stages = hdr->n_stages;
     for (int si = 0; si < n_stages; si++) {
-        const StageHdr sh = stages[hdr->stage_begin + si];
-        if (sh.wmask != cur_mask) {
+        const StageHdr& sh = stages[hdr->stage_begin + si];  // read in place (uniform scalar loads)
+        if (sh.wave_local != XCH_NONE) {
             int w_new[kMaxRegBits];
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) w_new[j] = sh.w[j];
-            const uint32_t tl_new = thread_part(sh.wmask, b, tid);
-            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_new, w_new);
-            cur_mask = sh.wmask;
+            const uint32_t tl_new = thread_part(sh.tpos, tb, tid);
+            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_new, w_new, sh.wave_local == XCH_WAVE);
             cur_tl = tl_new;
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
@@ -508,8 +516,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         }
     }
 
-    if (cur_mask != natural) {
-        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, (uint32_t)tid, wn);
+    if (hdr->final_wave_local != XCH_NONE) {
+        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_nat, wn, hdr->final_wave_local == XCH_WAVE);
     }
 #pragma unroll
     for (int k = 0; k < R; k++) {
@@ -531,11 +539,26 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 for (int w = 0; w < nw; w++) t += red[sl * 8 + w];
                 gpart[(int64_t)sl * gstride + (int64_t)blk] = t;
             }
+            __syncthreads();  // red[] is rewritten by the next block
         }
     }
+    }  // blocks
 }
 
 #undef QV_J1_CASES
+
+// Workgroups per CU pair of slots for a persistent grid (QVEC_PERSIST=k:
+// grid = k x CUs x 2); 0 launches one workgroup per block.
+static int persist_waves()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("QVEC_PERSIST");
+        v = e ? std::atoi(e) : 0;
+        if (v < 0) v = 0;
+    }
+    return v;
+}
 
 template <typename T, int RB, int NS>
 static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
@@ -552,7 +575,15 @@ static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
     }
     const uint64_t nblocks = 1ull << (n - b);
     const unsigned threads = 1u << (b - RB);
-    hipLaunchKernelGGL((k_block_reg<T, RB, NS>), dim3((unsigned)nblocks), dim3(threads), lds, st, s0, s1, d_hdr,
+    uint64_t grid = nblocks;
+    const int wave = persist_waves();
+    if (wave > 0) {
+        static int cus = 0;
+        if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
+        const uint64_t g = (uint64_t)wave * (uint64_t)cus * 2;
+        if (g < grid) grid = g;
+    }
+    hipLaunchKernelGGL((k_block_reg<T, RB, NS>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1, d_hdr,
                        d_stages, d_ops, d_mats, d_phase, gp, gs);
     return hipGetLastError();
 }

@@ -123,22 +123,83 @@ int window_index(const StageHdr& st, int r, int pos)
 // local positions in every thread's registers; the ops of the stage act
 // densely only inside the window (diagonal ops and controls may use any
 // position). Ops move between stages only past ops they commute with, by the
-// same rule as gates between passes. The first window is the one the block
-// is loaded with (the top r positions), and leftover window slots are filled
-// with those positions too, so that the last stage often needs no exchange
-// before the store.
-void plan_stages(PlanPass& pp, int b, int r)
+// same rule as gates between passes.
+//
+// Thread bits map to the positions outside the window: the low ones (lanes
+// of a wave) to the lowest free positions, the top ones (which wave of the
+// workgroup) to a set P of wave positions. While P stays out of the windows,
+// a window change only moves amplitudes between lanes of one wave, and the
+// exchange needs no workgroup barrier. P is chosen among the positions the
+// pass's ops use least, windows avoid it while they can, and it moves
+// (with a workgroup-wide exchange) only when an op needs one of its bits.
+// The first window is the load window (top positions outside P), and
+// leftover window slots are filled towards it so that the last stage often
+// needs no exchange before the store.
+void set_mapping(StageHdr& st, int b, int tb, uint32_t W, uint32_t P)
 {
-    const uint32_t natural = ((1u << r) - 1) << (b - r);
+    int j = 0;
+    for (int p = 0; p < b; p++)
+        if (W & (1u << p)) st.w[j++] = p;
+    st.wmask = W;
+    int i = 0;
+    for (int p = 0; p < b; p++)
+        if (!(W & (1u << p)) && !(P & (1u << p))) st.tpos[i++] = p;
+    for (int p = 0; p < b; p++)
+        if (P & (1u << p)) st.tpos[i++] = p;
+    (void)tb;
+}
+
+uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer)
+{
+    uint32_t P = 0;
+    for (int k = 0; k < wb; k++) {
+        int best = -1;
+        for (int p = b - 1; p >= 0; p--) {
+            if ((exclude | P) & (1u << p)) continue;
+            if (best < 0) { best = p; continue; }
+            const bool pp = prefer & (1u << p), pb = prefer & (1u << best);
+            const bool low_p = p < 3, low_b = best < 3;  // keep the contiguous qubits on lanes
+            if (low_p != low_b) { if (low_b) best = p; continue; }
+            if (use[p] < use[best] || (use[p] == use[best] && pp && !pb)) best = p;
+        }
+        if (best < 0) break;
+        P |= 1u << best;
+    }
+    return P;
+}
+
+void plan_stages(PlanPass& pp, int b, int r, int wave_mode)
+{
+    const int tb = b - r;
+    const int wb = (tb > 6 && wave_mode > 0) ? tb - 6 : 0;
+    const bool wave_ok = tb <= 6 || wb > 0;  // one wave per block, or wave positions kept apart
     std::vector<TileOp>& ops = pp.ops;
     std::vector<uint32_t> dn(ops.size()), dg(ops.size());
     for (size_t i = 0; i < ops.size(); i++) op_positions(ops[i], &dn[i], &dg[i]);
+    std::vector<int> use(b, 0);
+    for (size_t i = 0; i < ops.size(); i++)
+        for (int p = 0; p < b; p++) use[p] += (dn[i] >> p) & 1;
+
+    // load/store mapping: the default wave bits sit just above the lanes
+    const uint32_t default_P = wb ? (((1u << wb) - 1) << (tb - wb)) : 0;
+    uint32_t P = wave_mode == 2 ? pick_wave_positions(use, b, wb, 0, default_P) : default_P;
+    uint32_t natural = 0;
+    for (int p = b - 1, c = 0; p >= 0 && c < r; p--)
+        if (!(P & (1u << p))) {
+            natural |= 1u << p;
+            c++;
+        }
+    set_mapping(pp.hdr.nat, b, tb, natural, P);
+    pp.hdr.nat.wave_local = XCH_NONE;
+    const uint32_t P_nat = P;
+
     std::vector<char> done(ops.size(), 0);
     std::vector<TileOp> out;
     out.reserve(ops.size());
     pp.stages.clear();
     size_t first = 0;
     bool first_stage = true;
+    uint32_t prev_W = natural;
     while (true) {
         while (first < ops.size() && done[first]) first++;
         if (first >= ops.size()) break;
@@ -150,7 +211,8 @@ void plan_stages(PlanPass& pp, int b, int r)
             bool ok = !(dn[i] & (bd | bg)) && !(dg[i] & bd);
             if (ok) {
                 const uint32_t need = dn[i] & ~W;
-                if (popc(W | need) > r) ok = false;
+                // a wave position joins the window only for the stage's first op
+                if (popc(W | need) > r || ((need & P) && !taken.empty())) ok = false;
                 else W |= need;
             }
             if (ok) {
@@ -166,21 +228,29 @@ void plan_stages(PlanPass& pp, int b, int r)
             continue;
         }
         first_stage = false;
+        for (size_t i : taken)
+            for (int p = 0; p < b; p++) use[p] -= (dn[i] >> p) & 1;
         // leftover window slots: controls of the stage's CNOTs first (a CNOT
         // whose control is in the window is a plain register swap), then the
-        // load/store window
+        // load/store window, never a wave position
         for (size_t i : taken) {
             const TileOp& t = ops[i];
-            if (t.kind == T_XPERM && t.lctrl && !(t.lctrl & (t.lctrl - 1)) && popc(W) < r) W |= t.lctrl;
+            if (t.kind == T_XPERM && t.lctrl && !(t.lctrl & (t.lctrl - 1)) && popc(W) < r && !(t.lctrl & P))
+                W |= t.lctrl;
         }
         for (int p = b - 1; p >= 0 && popc(W) < r; p--)
-            if (natural & (1u << p)) W |= 1u << p;
+            if ((natural & (1u << p)) && !(P & (1u << p))) W |= 1u << p;
+        for (int p = 0; p < b && popc(W) < r; p++)
+            if (!(P & (1u << p))) W |= 1u << p;
         for (int p = 0; p < b && popc(W) < r; p++) W |= 1u << p;
         StageHdr st{};
-        int j = 0;
-        for (int p = 0; p < b; p++)
-            if (W & (1u << p)) st.w[j++] = p;
-        st.wmask = W;
+        const uint32_t P_prev = P, W_prev = prev_W;
+        if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat);  // an op needs a wave position
+        set_mapping(st, b, tb, W, P);
+        // exchange into this mapping: none if it is unchanged, within waves
+        // if the wave positions stay, else across the workgroup
+        st.wave_local = (W == W_prev && P == P_prev) ? XCH_NONE : (P == P_prev && wave_ok ? XCH_WAVE : XCH_BLOCK);
+        prev_W = W;
         st.op_begin = (int32_t)out.size();
         st.n_ops = (int32_t)taken.size();
         for (size_t i : taken) {
@@ -208,6 +278,8 @@ void plan_stages(PlanPass& pp, int b, int r)
         }
         pp.stages.push_back(st);
     }
+    pp.hdr.final_wave_local =
+        (prev_W == natural && P == P_nat) ? XCH_NONE : (P == P_nat && wave_ok ? XCH_WAVE : XCH_BLOCK);
     ops.swap(out);
     pp.hdr.n_stages = (int32_t)pp.stages.size();
 }
@@ -832,7 +904,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         h.n_grad = grads;
         if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
             if (opt.fuse_gates) fuse_ops(pp);
-            plan_stages(pp, b, opt.reg_bits);
+            plan_stages(pp, b, opt.reg_bits, opt.wave_mode);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
             set_reg_codes(pp);

@@ -117,12 +117,21 @@ struct PhaseTerm {
 // positions are w[0..r) are held by one thread (register bit j <-> position
 // w[j]); ops of the stage only act densely on those positions.
 constexpr int kMaxRegBits = 5;
+constexpr int kMaxThreadBits = 10;
 struct StageHdr {
     int32_t w[kMaxRegBits];
     uint32_t wmask;
     int32_t n_ops;
     int32_t op_begin;  // relative to the pass's first op
+    // thread bit i holds local position tpos[i]: lane bits first (ascending
+    // positions), then the wave-index bits
+    int32_t tpos[kMaxThreadBits];
+    int32_t wave_local;  // exchange into this mapping: XCH_NONE / XCH_WAVE / XCH_BLOCK
+    int32_t pad;
 };
+// Kinds of register-window exchange: none (same mapping), within each wave
+// (the wave positions stay, so no workgroup barrier), across the workgroup.
+enum XchKind : int32_t { XCH_NONE = 0, XCH_WAVE = 1, XCH_BLOCK = 2 };
 constexpr int kMaxGradPerPass = 128;
 
 constexpr int kMaxLocal = 16;
@@ -139,6 +148,9 @@ struct PassHdr {
     int32_t stage_begin;
     int32_t n_grad;     // gradient reads in this pass
     int32_t pad;
+    StageHdr nat;       // register kernel: the load/store mapping
+    int32_t final_wave_local;  // exchange back to `nat` before the store (XchKind)
+    int32_t pad3;
 };
 
 // One launch of a plan.
@@ -167,6 +179,9 @@ struct PlanOptions {
     bool prefuse = false;         // fuse one-qubit gates into two-qubit gates over the whole circuit first
     bool want_local = false;      // also bring controls / diagonal partners into a pass when there is room
     int want_reserve = 0;         // ... keeping this many local slots free for later targets
+    int wave_mode = 2;            // 0: workgroup-wide exchanges only; 1: fixed wave positions,
+                                  // within-wave exchanges while they hold; 2: wave positions picked
+                                  // from the pass's least-used positions
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its
