@@ -35,6 +35,34 @@ __device__ __forceinline__ T cmul2(T u0, T x, T u1, T y)
     return r;
 }
 
+// u0 x0 + u1 x1 + u2 x2 + u3 x3 as one multiply-add chain per component
+// (a row of a 4x4 update)
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T cdot4(T u0, T x0, T u1, T x1, T u2, T x2, T u3, T x3)
+{
+    T r;
+    r.x = u0.x * x0.x;
+    r.y = u0.x * x0.y;
+    r.x = fma_(-u0.y, x0.y, r.x);
+    r.y = fma_(u0.y, x0.x, r.y);
+    r.x = fma_(u1.x, x1.x, r.x);
+    r.y = fma_(u1.x, x1.y, r.y);
+    r.x = fma_(-u1.y, x1.y, r.x);
+    r.y = fma_(u1.y, x1.x, r.y);
+    r.x = fma_(u2.x, x2.x, r.x);
+    r.y = fma_(u2.x, x2.y, r.y);
+    r.x = fma_(-u2.y, x2.y, r.x);
+    r.y = fma_(u2.y, x2.x, r.y);
+    r.x = fma_(u3.x, x3.x, r.x);
+    r.y = fma_(u3.x, x3.y, r.y);
+    r.x = fma_(-u3.y, x3.y, r.x);
+    r.y = fma_(u3.y, x3.x, r.y);
+    return r;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T* p)
 {

@@ -17,22 +17,17 @@
 // the lowest local positions, which hold the lowest qubits and so
 // contiguous runs of memory); the planner starts and, when it can, ends on
 // that window.
+#include <cstdio>
 #include <cstdlib>
 
 #include "device_common.h"
 
 namespace qv {
 
-// 16-byte (complex128) or 8-byte (complex64) LDS slots; XOR-fold the higher
-// index bits into the bits that select the slot within a 256-byte row so
-// that lanes striding by a power of two land in different banks.
 template <typename T>
 __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
 {
-    constexpr int e = sizeof(T) == 16 ? 4 : 5;
-    constexpr uint32_t m = (1u << e) - 1;
-    const uint32_t h = l >> e;
-    return l ^ ((h ^ (h >> e) ^ (h >> (2 * e))) & m);
+    return lds_slot(l, sizeof(T) == 16 ? 4 : 5);
 }
 
 // Local index bits contributed by the thread index: thread bit i sits at
@@ -62,14 +57,15 @@ __device__ __forceinline__ uint32_t window_part(int k, const int (&w)[kMaxRegBit
     return l;
 }
 
-// Transpose the thread's registers from window w_old to w_new through LDS.
-// The swizzle is linear over XOR and the thread and window parts of an index
-// have disjoint bits, so slot(tl | wl) = slot(tl) ^ slot(wl): one per-thread
-// term and one uniform term per register.
+// Transpose the thread's registers from one mapping to another through LDS.
+// The slot map is linear over XOR and the thread and window parts of an
+// index have disjoint bits, so slot(tl | wl) = slot(tl) ^ slot(wl): one
+// per-thread term and one uniform term per register, the latter read from the
+// stage table (wo_old / wo_new: byte offsets, uniform scalar loads).
 template <typename T, int RB, int NS>
 __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, uint32_t tl_old,
-                                         const int (&w_old)[kMaxRegBits], uint32_t tl_new,
-                                         const int (&w_new)[kMaxRegBits], bool wave_only)
+                                         const uint32_t* __restrict__ wo_old, uint32_t tl_new,
+                                         const uint32_t* __restrict__ wo_new, bool wave_only)
 {
     constexpr int R = 1 << RB;
     unsigned char* base = reinterpret_cast<unsigned char*>(lds);
@@ -77,9 +73,7 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
     const uint32_t sn = lds_swizzle<T>(tl_new) * (uint32_t)sizeof(T);
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        // uniform part, kept in a scalar register
-        const uint32_t wk = __builtin_amdgcn_readfirstlane(lds_swizzle<T>(window_part<RB>(k, w_old)) * (uint32_t)sizeof(T));
-        const uint32_t off = so ^ wk;
+        const uint32_t off = so ^ wo_old[k];
 #pragma unroll
         for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
     }
@@ -89,23 +83,12 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
     else __syncthreads();
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        const uint32_t wk = __builtin_amdgcn_readfirstlane(lds_swizzle<T>(window_part<RB>(k, w_new)) * (uint32_t)sizeof(T));
-        const uint32_t off = sn ^ wk;
+        const uint32_t off = sn ^ wo_new[k];
 #pragma unroll
         for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
     }
     if (wave_only) wave_lds_sync();
     else __syncthreads();
-}
-
-// Control mask of an op, one bit per register: its local control bits are all set.
-template <int RB>
-__device__ __forceinline__ uint32_t ctrl_bits(uint32_t lctrl, uint32_t tl, const int (&w)[kMaxRegBits])
-{
-    uint32_t cm = 0;
-#pragma unroll
-    for (int k = 0; k < (1 << RB); k++) cm |= (((tl | window_part<RB>(k, w)) & lctrl) == lctrl ? 1u : 0u) << k;
-    return cm;
 }
 
 template <typename T, int RB, int NS, int J, bool CTRL>
@@ -201,12 +184,8 @@ __device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restr
 #pragma unroll
             for (int e = 0; e < 4; e++) x[e] = v[s][idx[e]];
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                w[r] = cmul2(u[4 * r], x[0], u[4 * r + 1], x[1]);
-                const T t = cmul2(u[4 * r + 2], x[2], u[4 * r + 3], x[3]);
-                w[r].x += t.x;
-                w[r].y += t.y;
-            }
+            for (int r = 0; r < 4; r++)
+                w[r] = cdot4(u[4 * r], x[0], u[4 * r + 1], x[1], u[4 * r + 2], x[2], u[4 * r + 3], x[3]);
 #pragma unroll
             for (int e = 0; e < 4; e++) v[s][idx[e]] = CTRL ? (on ? w[e] : x[e]) : w[e];
         }
@@ -263,11 +242,13 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], int gen)
 
 // Occupancy target per SIMD: the narrow single-state variant is held to
 // 128 VGPRs so that two 512-thread workgroups (LDS-limited) fill a CU.
-template <int RB, int NS>
-constexpr int block_waves_per_eu() { return (RB == 3 && NS == 1) ? 4 : 1; }
+// With prefetch (PF) the next block's registers are live as well, and the
+// target drops to three waves per SIMD.
+template <int RB, int NS, bool PF>
+constexpr int block_waves_per_eu() { return (RB == 3 && NS == 1) ? (PF ? 3 : 4) : 1; }
 
-template <typename T, int RB, int NS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<RB, NS>())))
+template <typename T, int RB, int NS, bool PF>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<RB, NS, PF>())))
 void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                                                    const PassHdr* __restrict__ hdr,
                                                    const StageHdr* __restrict__ stages,
@@ -288,37 +269,68 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const uint64_t nblocks = 1ull << hdr->n_outer;
-    // A grid smaller than the block count walks the blocks in strides.
-    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    uint64_t base = 0;
-    for (int j = 0; j < hdr->n_outer; j++) base |= ((blk >> j) & 1ull) << hdr->outer_q[j];
 
     // Load/store mapping (lanes on the lowest positions, see the planner).
     int wn[kMaxRegBits];
 #pragma unroll
     for (int j = 0; j < kMaxRegBits; j++) wn[j] = hdr->nat.w[j];
     const uint32_t tl_nat = thread_part(hdr->nat.tpos, tb, tid);
-    uint64_t gt = base;
-    for (int i = 0; i < tb; i++) gt |= (uint64_t)((tid >> i) & 1) << hdr->local_q[hdr->nat.tpos[i]];
+    uint64_t tg = 0;  // the thread's bits of the global index
+    for (int i = 0; i < tb; i++) tg |= (uint64_t)((tid >> i) & 1) << hdr->local_q[hdr->nat.tpos[i]];
     int qr[RB];  // global qubits of the load window
 #pragma unroll
     for (int j = 0; j < RB; j++) qr[j] = hdr->local_q[wn[j]];
+    auto block_base = [&](uint64_t blk) {
+        uint64_t bb = 0;
+        for (int j = 0; j < hdr->n_outer; j++) bb |= ((blk >> j) & 1ull) << hdr->outer_q[j];
+        return bb;
+    };
+    auto load_block = [&](T (&dst)[NS][R], uint64_t g0) {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            uint64_t g = g0;
+#pragma unroll
+            for (int j = 0; j < RB; j++)
+                if ((k >> j) & 1) g |= 1ull << qr[j];
+            dst[0][k] = ld_nt(s0 + g);
+            if (NS == 2) dst[NS - 1][k] = ld_nt(s1 + g);
+        }
+    };
+
+    // With PF the grid is sized to the resident workgroups and each one
+    // issues the loads of its next block before working on the current one,
+    // so that HBM reads overlap the register work.
+    T nx[PF ? NS : 1][PF ? R : 1];
+    if constexpr (PF) {
+        if (blockIdx.x < nblocks) load_block(nx, block_base(blockIdx.x) | tg);
+        // Nothing outstanding at the loop entry: the loop's own waits then
+        // count only the loop's loads and stores.
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    // A grid smaller than the block count walks the blocks in strides.
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const uint64_t base = block_base(blk);
+    const uint64_t gt = base | tg;
 
     T v[NS][R];
+    if constexpr (PF) {
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        uint64_t g = gt;
+        for (int s = 0; s < NS; s++)
 #pragma unroll
-        for (int j = 0; j < RB; j++)
-            if ((k >> j) & 1) g |= 1ull << qr[j];
-        v[0][k] = ld_nt(s0 + g);
-        if (NS == 2) v[NS - 1][k] = ld_nt(s1 + g);
+            for (int k = 0; k < R; k++) v[s][k] = nx[s][k];
+        // unconditional, so that the wait for these loads has a fixed
+        // count (the last block reloads itself; those values go unused)
+        const uint64_t nb = blk + gridDim.x < nblocks ? blk + gridDim.x : blk;
+        load_block(nx, block_base(nb) | tg);
+    } else {
+        load_block(v, gt);
     }
 
     int cur_w[kMaxRegBits];
 #pragma unroll
     for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = wn[j];
     uint32_t cur_tl = tl_nat;
+    const uint32_t* cur_wo = hdr->nat.woff;
 
     const TileOp* po = ops + hdr->op_begin;
     const int n_stages = hdr->n_stages;
@@ -329,8 +341,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) w_new[j] = sh.w[j];
             const uint32_t tl_new = thread_part(sh.tpos, tb, tid);
-            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_new, w_new, sh.wave_local == XCH_WAVE);
+            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, tl_new, sh.woff, sh.wave_local == XCH_WAVE);
             cur_tl = tl_new;
+            cur_wo = sh.woff;
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
         }
@@ -338,11 +351,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
             const TileOp op = po[sh.op_begin + o];
             if ((base & op.gctrl) != op.gctrl) continue;  // uniform over the block
             const int code = op.code;
-            const uint32_t cm = (code >= RC_D1C && code < RC_D1C + 5) || (code >= RC_XC && code < RC_XC + 5) ||
-                                        (code >= RC_D2C && code < RC_SW) || (code >= RC_SWC && code < RC_DIAG) ||
-                                        (code == RC_DIAG && op.lctrl)
-                                    ? ctrl_bits<RB>(op.lctrl, cur_tl, cur_w)
-                                    : ~0u;
+            // registers the op acts on (all, for ops without local controls)
+            const uint32_t cm = (cur_tl & op.tctrl) == op.tctrl ? op.kmask : 0u;
             switch (code) {
 #define QV_C1(BASE, J, STMT) \
     case BASE + J:           \
@@ -517,7 +527,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     }
 
     if (hdr->final_wave_local != XCH_NONE) {
-        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_w, tl_nat, wn, hdr->final_wave_local == XCH_WAVE);
+        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, tl_nat, hdr->nat.woff, hdr->final_wave_local == XCH_WAVE);
     }
 #pragma unroll
     for (int k = 0; k < R; k++) {
@@ -560,32 +570,81 @@ static int persist_waves()
     return v;
 }
 
-template <typename T, int RB, int NS>
-static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
+// Register prefetch of the next block. Measured on the 29-qubit benchmark it
+// pays for complex64 (smaller registers, three waves per SIMD) and not for
+// complex128 (the variant needs all 256 VGPRs); QVEC_PREFETCH=0/1 overrides.
+template <typename T>
+static bool prefetch_on()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("QVEC_PREFETCH");
+        v = e ? (e[0] == '1' ? 1 : 0) : (sizeof(T) == 8 ? 1 : 0);
+    }
+    return v == 1;
+}
+
+static int cu_count()
+{
+    static int cus = 0;
+    if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
+    return cus;
+}
+
+template <typename T, int RB, int NS, bool PF>
+static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
                                const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
                                int64_t gs, hipStream_t st)
 {
+    const void* fn = reinterpret_cast<const void*>(&k_block_reg<T, RB, NS, PF>);
     static size_t attr_bytes = 0;
     const size_t lds = (size_t)NS * ((size_t)1 << b) * sizeof(T);
     if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_block_reg<T, RB, NS>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_bytes = lds;
     }
     const uint64_t nblocks = 1ull << (n - b);
     const unsigned threads = 1u << (b - RB);
     uint64_t grid = nblocks;
-    const int wave = persist_waves();
-    if (wave > 0) {
-        static int cus = 0;
-        if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 256;
-        const uint64_t g = (uint64_t)wave * (uint64_t)cus * 2;
+    if (PF) {
+        // one workgroup per resident slot
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)threads, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        const char* pe = std::getenv("QVEC_PF_PER_CU");  // experiment: workgroups per CU
+        if (pe && std::atoi(pe) > 0) per_cu = std::atoi(pe);
+        static bool said = false;
+        if (!said && std::getenv("QVEC_VERBOSE")) {
+            std::fprintf(stderr, "k_block_reg prefetch: %d workgroups per CU, %u threads, %zu B LDS\n", per_cu,
+                         threads, lds);
+            said = true;
+        }
+        const uint64_t g = (uint64_t)per_cu * (uint64_t)cu_count();
         if (g < grid) grid = g;
+    } else {
+        const int wave = persist_waves();
+        if (wave > 0) {
+            const uint64_t g = (uint64_t)wave * (uint64_t)cu_count() * 2;
+            if (g < grid) grid = g;
+        }
     }
-    hipLaunchKernelGGL((k_block_reg<T, RB, NS>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1, d_hdr,
+    hipLaunchKernelGGL((k_block_reg<T, RB, NS, PF>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1, d_hdr,
                        d_stages, d_ops, d_mats, d_phase, gp, gs);
     return hipGetLastError();
+}
+
+template <typename T, int RB, int NS>
+static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
+                               const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
+                               int64_t gs, hipStream_t st)
+{
+    if constexpr (NS == 1) {
+        if (prefetch_on<T>())
+            return launch_reg_k<T, RB, NS, true>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+    }
+    return launch_reg_k<T, RB, NS, false>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
 }
 
 template <typename T>

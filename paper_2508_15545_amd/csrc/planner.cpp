@@ -135,7 +135,7 @@ int window_index(const StageHdr& st, int r, int pos)
 // The first window is the load window (top positions outside P), and
 // leftover window slots are filled towards it so that the last stage often
 // needs no exchange before the store.
-void set_mapping(StageHdr& st, int b, int tb, uint32_t W, uint32_t P)
+void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int elem)
 {
     int j = 0;
     for (int p = 0; p < b; p++)
@@ -146,7 +146,13 @@ void set_mapping(StageHdr& st, int b, int tb, uint32_t W, uint32_t P)
         if (!(W & (1u << p)) && !(P & (1u << p))) st.tpos[i++] = p;
     for (int p = 0; p < b; p++)
         if (P & (1u << p)) st.tpos[i++] = p;
-    (void)tb;
+    // exchange-buffer byte offsets of the registers' window bits
+    for (int k = 0; k < (1 << r); k++) {
+        uint32_t l = 0;
+        for (int jj = 0; jj < r; jj++)
+            if ((k >> jj) & 1) l |= 1u << st.w[jj];
+        st.woff[k] = lds_slot(l, elem == 16 ? 4 : 5) * (uint32_t)elem;
+    }
 }
 
 uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer)
@@ -168,7 +174,7 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
     return P;
 }
 
-void plan_stages(PlanPass& pp, int b, int r, int wave_mode)
+void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
 {
     const int tb = b - r;
     const int wb = (tb > 6 && wave_mode > 0) ? tb - 6 : 0;
@@ -189,7 +195,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode)
             natural |= 1u << p;
             c++;
         }
-    set_mapping(pp.hdr.nat, b, tb, natural, P);
+    set_mapping(pp.hdr.nat, b, natural, P, r, elem);
     pp.hdr.nat.wave_local = XCH_NONE;
     const uint32_t P_nat = P;
 
@@ -246,7 +252,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode)
         StageHdr st{};
         const uint32_t P_prev = P, W_prev = prev_W;
         if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat);  // an op needs a wave position
-        set_mapping(st, b, tb, W, P);
+        set_mapping(st, b, W, P, r, elem);
         // exchange into this mapping: none if it is unchanged, within waves
         // if the wave positions stay, else across the workgroup
         st.wave_local = (W == W_prev && P == P_prev) ? XCH_NONE : (P == P_prev && wave_ok ? XCH_WAVE : XCH_BLOCK);
@@ -303,9 +309,29 @@ int32_t reg_code(const TileOp& t)
     }
 }
 
-void set_reg_codes(PlanPass& pp)
+void set_reg_codes(PlanPass& pp, int r)
 {
-    for (TileOp& t : pp.ops) t.code = reg_code(t);
+    for (TileOp& t : pp.ops) {
+        t.code = reg_code(t);
+        t.tctrl = 0;
+        t.kmask = (1u << r) - 1;
+    }
+    // local controls split into the thread's part and a register mask
+    for (const StageHdr& st : pp.stages) {
+        for (int o = st.op_begin; o < st.op_begin + st.n_ops; o++) {
+            TileOp& t = pp.ops[o];
+            const uint32_t wc = t.lctrl & st.wmask;
+            t.tctrl = t.lctrl & ~st.wmask;
+            uint32_t km = 0;
+            for (int k = 0; k < (1 << r); k++) {
+                uint32_t l = 0;
+                for (int j = 0; j < r; j++)
+                    if ((k >> j) & 1) l |= 1u << st.w[j];
+                if ((l & wc) == wc) km |= 1u << k;
+            }
+            t.kmask = km;
+        }
+    }
 }
 
 // ------------------------------------------------------------ fusion ---
@@ -904,10 +930,10 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         h.n_grad = grads;
         if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
             if (opt.fuse_gates) fuse_ops(pp);
-            plan_stages(pp, b, opt.reg_bits, opt.wave_mode);
+            plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
-            set_reg_codes(pp);
+            set_reg_codes(pp, opt.reg_bits);
         }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
         passes.push_back(std::move(pp));

@@ -73,6 +73,11 @@ struct TileOp {
     int32_t j0, j1;    // register-window bits of a / c (register kernel; j0 < j1)
     int32_t cnt;       // T_PHASE: number of phase terms
     int32_t code;      // register kernel: flat dispatch code (RegCode)
+    // register kernel: the op acts on register k of a thread iff the thread's
+    // bits cover tctrl (local controls outside the window) and bit k of
+    // kmask is set (registers whose window bits cover the other controls)
+    uint32_t tctrl;
+    uint32_t kmask;
     int32_t pad2;
 };
 
@@ -128,7 +133,20 @@ struct StageHdr {
     int32_t tpos[kMaxThreadBits];
     int32_t wave_local;  // exchange into this mapping: XCH_NONE / XCH_WAVE / XCH_BLOCK
     int32_t pad;
+    // byte offset in the exchange buffer of register k's window bits
+    // (lds_slot of the window part, times the amplitude size)
+    uint32_t woff[1 << kMaxRegBits];
 };
+
+// LDS slot of local index l in the register kernel's exchange buffer: the
+// index bits above the e lowest (e = 4 for 16-byte, 5 for 8-byte amplitudes,
+// so that 2^e slots make a 256-byte row) are XOR-folded into the e lowest,
+// which spreads power-of-two strides over the banks. The map is linear over
+// XOR, so the slot of (thread bits | window bits) is the XOR of their slots.
+constexpr uint32_t lds_slot(uint32_t l, int e)
+{
+    return l ^ (((l >> e) ^ (l >> (2 * e)) ^ (l >> (3 * e))) & ((1u << e) - 1));
+}
 // Kinds of register-window exchange: none (same mapping), within each wave
 // (the wave positions stay, so no workgroup barrier), across the workgroup.
 enum XchKind : int32_t { XCH_NONE = 0, XCH_WAVE = 1, XCH_BLOCK = 2 };
