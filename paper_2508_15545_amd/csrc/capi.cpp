@@ -336,7 +336,8 @@ sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, TableOf
         for (const StageHdr& sh : p.stages) S[is++] = sh;
         for (const TileOp& op : p.ops) {
             TileOp t = op;
-            t.mat += (int32_t)(t.kind == T_PHASE ? ip : im);
+            t.mat += (int32_t)im;
+            if (t.kind == T_PHASE) t.aux += (int32_t)ip;
             O[io++] = t;
         }
         for (const PhaseTerm& pt : p.phase) P[ip++] = pt;

@@ -57,6 +57,46 @@ __device__ __forceinline__ uint32_t window_part(int k, const int (&w)[kMaxRegBit
     return l;
 }
 
+// e^{2 pi i x} for x in turns (reduced to [-1/2, 1/2] first)
+template <typename T>
+__device__ __forceinline__ T cis_turns(double x)
+{
+    x -= rint(x);
+    T f;
+    if constexpr (sizeof(T) == 16) {
+        double sn, cs;
+        sincospi(2.0 * x, &sn, &cs);
+        f.x = cs;
+        f.y = sn;
+    } else {
+        float sn, cs;
+        sincospif((float)(2.0 * x), &sn, &cs);
+        f.x = cs;
+        f.y = sn;
+    }
+    return f;
+}
+
+// The op fields every op needs, in the order they lead TileOp.
+struct OpHot {
+    int32_t code;
+    int32_t mat;
+    uint32_t tctrl;
+    uint32_t kmask;
+    uint64_t gctrl;
+};
+
+__device__ __forceinline__ OpHot op_hot(const TileOp* p)
+{
+    OpHot h;
+    h.code = p->code;
+    h.mat = p->mat;
+    h.tctrl = p->tctrl;
+    h.kmask = p->kmask;
+    h.gctrl = p->gctrl;
+    return h;
+}
+
 // Transpose the thread's registers from one mapping to another through LDS.
 // The slot map is linear over XOR and the thread and window parts of an
 // index have disjoint bits, so slot(tl | wl) = slot(tl) ^ slot(wl): one
@@ -347,12 +387,19 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
         }
-        for (int o = 0; o < sh.n_ops; o++) {
-            const TileOp op = po[sh.op_begin + o];
-            if ((base & op.gctrl) != op.gctrl) continue;  // uniform over the block
-            const int code = op.code;
+        // The per-op fields of the next op are loaded while the current op
+        // runs, so that each op waits for one round of scalar loads (its
+        // matrix) instead of three.
+        const TileOp* sop = po + sh.op_begin;
+        const int nops = sh.n_ops;
+        OpHot cur = op_hot(sop);
+        for (int o = 0; o < nops; o++) {
+            const OpHot nxt = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+            const TileOp& op = sop[o];  // the other fields, read where a case needs them
+            if ((base & cur.gctrl) == cur.gctrl) {  // uniform over the block
+            const int code = cur.code;
             // registers the op acts on (all, for ops without local controls)
-            const uint32_t cm = (cur_tl & op.tctrl) == op.tctrl ? op.kmask : 0u;
+            const uint32_t cm = (cur_tl & cur.tctrl) == cur.tctrl ? cur.kmask : 0u;
             switch (code) {
 #define QV_C1(BASE, J, STMT) \
     case BASE + J:           \
@@ -370,14 +417,14 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     QV_PAIRS(BASE, F) \
     QV_C2(BASE, 1, 0, F) QV_C2(BASE, 2, 0, F) QV_C2(BASE, 3, 0, F) QV_C2(BASE, 4, 0, F) QV_C2(BASE, 2, 1, F) \
     QV_C2(BASE, 3, 1, F) QV_C2(BASE, 4, 1, F) QV_C2(BASE, 3, 2, F) QV_C2(BASE, 4, 2, F) QV_C2(BASE, 4, 3, F)
-#define QV_M2 mats[op.mat], mats[op.mat + 1], mats[op.mat + 2], mats[op.mat + 3]
+#define QV_M2 mats[cur.mat], mats[cur.mat + 1], mats[cur.mat + 2], mats[cur.mat + 3]
 #define F_D1(J) reg_dense1<T, RB, NS, J, false>(v, QV_M2, cm)
 #define F_D1C(J) reg_dense1<T, RB, NS, J, true>(v, QV_M2, cm)
 #define F_X(J) reg_xperm<T, RB, NS, J, false>(v, cm, one)
 #define F_XC(J) reg_xperm<T, RB, NS, J, true>(v, cm, one)
 #define F_CX(A, B) reg_cx<T, RB, NS, A, B>(v, one)
-#define F_D2(A, B) reg_dense2<T, RB, NS, A, B, false>(v, mats + op.mat, cm)
-#define F_D2C(A, B) reg_dense2<T, RB, NS, A, B, true>(v, mats + op.mat, cm)
+#define F_D2(A, B) reg_dense2<T, RB, NS, A, B, false>(v, mats + cur.mat, cm)
+#define F_D2C(A, B) reg_dense2<T, RB, NS, A, B, true>(v, mats + cur.mat, cm)
 #define F_SW(A, B) reg_swap<T, RB, NS, A, B, false>(v, cm, one)
 #define F_SWC(A, B) reg_swap<T, RB, NS, A, B, true>(v, cm, one)
                 QV_ALL1(RC_D1, F_D1)
@@ -390,7 +437,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 QV_PAIRS(RC_SW, F_SW)
                 QV_PAIRS(RC_SWC, F_SWC)
             case RC_DIAG: {
-                const T d0 = mats[op.mat], d1 = mats[op.mat + 1], dd2 = mats[op.mat + 2], d3 = mats[op.mat + 3];
+                const T d0 = mats[cur.mat], d1 = mats[cur.mat + 1], dd2 = mats[cur.mat + 2], d3 = mats[cur.mat + 3];
                 const int a = op.a, c = op.c;
                 const bool ctrl = op.lctrl != 0;
                 const int ua = a < 0 ? (op.oa >= 0 ? (int)((base >> op.oa) & 1) : 0) : 0;
@@ -413,70 +460,47 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 break;
             }
             case RC_PHASE: {
-                // A: the part of the angle fixed for this thread; eff[j] and
-                // qq[j][j2]: coefficients of window bits j and j & j2.
-                double A = 0, eff[RB], qq[RB][RB];
+                // angle(k) = A + sum_j k_j eff[j] + (window-only part, tabulated
+                // as unit complex numbers at mats[cur.mat + k]); A and eff[j]
+                // depend on the thread's bits (terms padded to groups of 4)
+                double A = 0, eff[RB];
+#pragma unroll
+                for (int j = 0; j < RB; j++) eff[j] = 0;
+                const PhaseTerm* pt = phase + op.aux;
+                const int cnt = op.cnt;
+                for (int t = 0; t < cnt; t += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const PhaseTerm term = pt[t + u];
+                        auto bitval = [&](int p) -> int {
+                            return p < 64 ? (int)((cur_tl >> p) & 1u) : (int)((base >> (p - 64)) & 1ull);
+                        };
+                        if (term.kind == PH_THREAD) {
+                            int bv = bitval(term.p1);
+                            if (term.p2 >= 0) bv &= bitval(term.p2);
+                            A += bv ? term.th : 0.0;
+                        } else if (term.kind == PH_MIXED) {
+                            const double x = bitval(term.p1) ? term.th : 0.0;
+#pragma unroll
+                            for (int j = 0; j < RB; j++)
+                                if (j == term.j) eff[j] += x;
+                        }
+                    }
+                }
+                // e^{2 pi i angle(k)} as products of RB + 1 unit factors
+                T f[R];
+                f[0] = cis_turns<T>(A);
 #pragma unroll
                 for (int j = 0; j < RB; j++) {
-                    eff[j] = 0;
+                    const T e = cis_turns<T>(eff[j]);
 #pragma unroll
-                    for (int j2 = 0; j2 < RB; j2++) qq[j][j2] = 0;
-                }
-                const PhaseTerm* pt = phase + op.mat;
-                for (int t = 0; t < op.cnt; t++) {
-                    const PhaseTerm term = pt[t];
-                    auto bitval = [&](int p) -> int {
-                        return p < 64 ? (int)((cur_tl >> p) & 1u) : (int)((base >> (p - 64)) & 1ull);
-                    };
-                    if (term.kind == PH_THREAD) {
-                        int bv = bitval(term.p1);
-                        if (term.p2 >= 0) bv &= bitval(term.p2);
-                        A += bv ? term.th : 0.0;
-                    } else if (term.kind == PH_MIXED) {
-                        const double x = bitval(term.p1) ? term.th : 0.0;
-#pragma unroll
-                        for (int j = 0; j < RB; j++)
-                            if (j == term.j) eff[j] += x;
-                    } else if (term.kind == PH_WLIN) {
-#pragma unroll
-                        for (int j = 0; j < RB; j++)
-                            if (j == term.j) eff[j] += term.th;
-                    } else if (term.kind == PH_WQUAD) {
-#pragma unroll
-                        for (int j = 0; j < RB; j++)
-#pragma unroll
-                            for (int j2 = j + 1; j2 < RB; j2++)
-                                if (j == term.j && j2 == term.j2) qq[j][j2] += term.th;
-                    } else {
-                        A += term.th;
-                    }
+                    for (int k = 0; k < (1 << j); k++) f[k | (1 << j)] = cmul(f[k], e);
                 }
 #pragma unroll
                 for (int k = 0; k < R; k++) {
-                    double ang = A;
+                    const T g = cmul(mats[cur.mat + k], f[k]);
 #pragma unroll
-                    for (int j = 0; j < RB; j++) {
-                        if (!((k >> j) & 1)) continue;
-                        ang += eff[j];
-#pragma unroll
-                        for (int j2 = j + 1; j2 < RB; j2++)
-                            if ((k >> j2) & 1) ang += qq[j][j2];
-                    }
-                    ang -= rint(ang);  // turns, in [-1/2, 1/2]
-                    T f;
-                    if constexpr (sizeof(T) == 16) {
-                        double sn, cs;
-                        sincospi(2.0 * ang, &sn, &cs);
-                        f.x = cs;
-                        f.y = sn;
-                    } else {
-                        float sn, cs;
-                        sincospif((float)(2.0 * ang), &sn, &cs);
-                        f.x = cs;
-                        f.y = sn;
-                    }
-#pragma unroll
-                    for (int s = 0; s < NS; s++) v[s][k] = cmul(f, v[s][k]);
+                    for (int s = 0; s < NS; s++) v[s][k] = cmul(g, v[s][k]);
                 }
                 break;
             }
@@ -523,6 +547,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #undef QV_C1
             default: break;
             }
+            }
+            cur = nxt;
         }
     }
 

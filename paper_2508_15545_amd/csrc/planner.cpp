@@ -714,12 +714,25 @@ TileOp make_phase(const std::vector<TileOp>& run, const StageHdr& st, int r, Pla
     t.j0 = t.j1 = -1;
     t.gen = GEN_NONE;
     t.slot = -1;
-    t.mat = (int32_t)pp.phase.size();
+    // window-only part (constant, window-linear, window-quadratic terms) as a
+    // table of 2^r unit complex numbers, one per register
+    std::vector<double> wang(1u << r, 0.0);
+    t.aux = (int32_t)pp.phase.size();
     for (const auto& kv : acc) {
         double th = kv.second - std::nearbyint(kv.second);  // angles are periodic in turns
         if (th == 0.0) continue;
+        const int kind = kv.first[0];
+        if (kind == PH_CONST || kind == PH_WLIN || kind == PH_WQUAD) {
+            for (int k = 0; k < (1 << r); k++) {
+                const bool on = kind == PH_CONST ||
+                                (kind == PH_WLIN && ((k >> kv.first[1]) & 1)) ||
+                                (kind == PH_WQUAD && ((k >> kv.first[1]) & 1) && ((k >> kv.first[2]) & 1));
+                if (on) wang[k] += th;
+            }
+            continue;
+        }
         PhaseTerm pt{};
-        pt.kind = kv.first[0];
+        pt.kind = kind;
         pt.j = kv.first[1];
         pt.j2 = kv.first[2];
         pt.p1 = kv.first[3];
@@ -727,7 +740,19 @@ TileOp make_phase(const std::vector<TileOp>& run, const StageHdr& st, int r, Pla
         pt.th = th;
         pp.phase.push_back(pt);
     }
-    t.cnt = (int32_t)(pp.phase.size() - t.mat);
+    while ((pp.phase.size() - t.aux) % 4) {
+        PhaseTerm pad{};
+        pad.kind = PH_CONST;
+        pad.j = pad.j2 = pad.p1 = pad.p2 = -1;
+        pad.th = 0.0;
+        pp.phase.push_back(pad);
+    }
+    t.cnt = (int32_t)(pp.phase.size() - t.aux);
+    t.mat = (int32_t)pp.mats.size();
+    for (int k = 0; k < (1 << r); k++) {
+        const double a = wang[k] - std::nearbyint(wang[k]);
+        pp.mats.push_back(cd(std::cos(2.0 * M_PI * a), std::sin(2.0 * M_PI * a)));
+    }
     return t;
 }
 

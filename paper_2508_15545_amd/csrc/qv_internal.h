@@ -61,24 +61,25 @@ enum TileKind : int32_t {
 };
 
 struct TileOp {
+    // The register kernel's per-op fields come first (one scalar load).
+    int32_t code;      // register kernel: flat dispatch code (RegCode)
+    int32_t mat;       // offset of the matrix in the pass matrix array (complex
+                       // entries); T_PHASE: its table of 2^r window phases
+    // register kernel: the op acts on register k of a thread iff the thread's
+    // bits cover tctrl (local controls outside the window) and bit k of
+    // kmask is set (registers whose window bits cover the other controls)
+    uint32_t tctrl;
+    uint32_t kmask;
+    uint64_t gctrl;    // control bits outside the block (global): block base must have them
     int32_t kind;
     int32_t a, c;      // local positions (-1: not local)
     int32_t oa, oc;    // global qubits for non-local diagonal bits (-1: none)
     uint32_t lctrl;    // control bits inside the block (local positions)
     int32_t gen;       // T_GRAD: GEN_X / GEN_Y / GEN_Z
     int32_t slot;      // T_GRAD: partial row
-    uint64_t gctrl;    // control bits outside the block (global): block base must have them
-    int32_t mat;       // offset of the matrix in the pass matrix array (complex
-                       // entries); T_PHASE: offset of its first phase term
     int32_t j0, j1;    // register-window bits of a / c (register kernel; j0 < j1)
-    int32_t cnt;       // T_PHASE: number of phase terms
-    int32_t code;      // register kernel: flat dispatch code (RegCode)
-    // register kernel: the op acts on register k of a thread iff the thread's
-    // bits cover tctrl (local controls outside the window) and bit k of
-    // kmask is set (registers whose window bits cover the other controls)
-    uint32_t tctrl;
-    uint32_t kmask;
-    int32_t pad2;
+    int32_t cnt;       // T_PHASE: number of thread terms (a multiple of 4)
+    int32_t aux;       // T_PHASE: offset of its first thread term in the phase array
 };
 
 // Flat dispatch codes of the register kernel: one switch case per op kind,
@@ -103,6 +104,9 @@ enum RegCode : int32_t {
 // One term of a phase polynomial, angles in turns (1 = 2 pi). The phase of
 // an amplitude is the sum of its terms; bit(p) is the amplitude's bit at
 // local position p (p < 64) or at global qubit p - 64 (outside the block).
+// The register kernel gets the terms that involve thread or outer bits
+// (PH_THREAD, PH_MIXED; PH_CONST with th = 0 pads to groups of 4); the
+// window-only terms are tabulated per register.
 enum PhaseKind : int32_t {
     PH_THREAD = 0,  // A += th * bit(p1) * bit(p2) (p2 < 0: linear); p1, p2 outside the window
     PH_MIXED = 1,   // eff[j] += th * bit(p1): window bit j times a bit outside the window
