@@ -596,16 +596,16 @@ static int persist_waves()
     return v;
 }
 
-// Register prefetch of the next block. Measured on the 29-qubit benchmark it
-// pays for complex64 (smaller registers, three waves per SIMD) and not for
-// complex128 (the variant needs all 256 VGPRs); QVEC_PREFETCH=0/1 overrides.
+// Register prefetch of the next block (QVEC_PREFETCH=1). Off by default:
+// its extra registers cost a wave per SIMD, and on the 29-qubit benchmark
+// occupancy hides the load latency better than the prefetch does.
 template <typename T>
 static bool prefetch_on()
 {
     static int v = -1;
     if (v < 0) {
         const char* e = std::getenv("QVEC_PREFETCH");
-        v = e ? (e[0] == '1' ? 1 : 0) : (sizeof(T) == 8 ? 1 : 0);
+        v = e ? (e[0] == '1' ? 1 : 0) : 0;
     }
     return v == 1;
 }

@@ -31,11 +31,12 @@ namespace qv {
 
 int default_block_qubits(int n, int elem_bytes, int n_states)
 {
-    // 64 KiB of LDS per workgroup (4096 complex128 / 8192 complex64
-    // amplitudes, halved when the adjoint carries two states): two
-    // workgroups share a CU. Measured on MI355X, this beats one 128 KiB
-    // workgroup per CU even though the larger block needs fewer passes.
-    const int lb = n_states == 2 ? (elem_bytes == 16 ? 11 : 12) : (elem_bytes == 16 ? 12 : 13);
+    // 2^12 amplitudes per block: 64 KiB of LDS for complex128 (two
+    // workgroups per CU, the register file allows no more), 32 KiB for
+    // complex64 (four per CU at four waves per SIMD). Measured on MI355X,
+    // occupancy beats the fewer passes of larger blocks. The adjoint carries
+    // two states and halves the complex128 block.
+    const int lb = n_states == 2 ? (elem_bytes == 16 ? 11 : 12) : 12;
     return std::min(n, lb);
 }
 
