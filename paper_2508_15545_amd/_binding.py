@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes
+import struct
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -134,11 +135,37 @@ def gate_struct(g) -> SvGate:
     return s
 
 
+# op, qubits[2], n_controls, controls[2], param_index, reserved, angles[3]
+_GATE_HEAD = struct.Struct("<8i3d")
+
+
 def gate_array(circuit) -> "ctypes.Array[SvGate]":
-    arr = (SvGate * max(1, len(circuit)))()
+    """Gate list -> contiguous sv_gate array (packed with struct; the ctypes
+    array keeps its byte buffer alive)."""
+    circuit = list(circuit)
+    n = len(circuit)
+    size = ctypes.sizeof(SvGate)
+    mat_off = SvGate.matrix.offset
+    buf = bytearray(size * max(1, n))
+    pack = _GATE_HEAD.pack_into
     for i, g in enumerate(circuit):
-        arr[i] = gate_struct(g)
-    return arr
+        op = OPS.get(g.op)
+        if op is None:
+            raise ValueError(f"unknown op {g.op!r}")
+        q = g.qubits
+        ctrls = getattr(g, "controls", None) or ()
+        c0 = ctrls[0] if len(ctrls) > 0 else 0
+        c1 = ctrls[1] if len(ctrls) > 1 else 0
+        p = g.params
+        base = i * size
+        if g.op in ("mat1", "mat2"):
+            pack(buf, base, op, q[0], q[1] if len(q) > 1 else 0, len(ctrls), c0, c1, g.param_index, 0, 0.0, 0.0, 0.0)
+            struct.pack_into(f"<{len(p)}d", buf, base + mat_off, *p)
+        else:
+            a = (tuple(p[:3]) + (0.0, 0.0, 0.0)) if len(p) < 3 else p
+            pack(buf, base, op, q[0], q[1] if len(q) > 1 else 0, len(ctrls), c0, c1, g.param_index, 0,
+                 a[0], a[1], a[2])
+    return (SvGate * max(1, n)).from_buffer(buf)
 
 
 def pauli_array(terms) -> "ctypes.Array[SvPauli]":

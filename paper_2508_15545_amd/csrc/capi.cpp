@@ -758,6 +758,44 @@ sv_status sv_apply_pauli_sum(sv_state s, const sv_pauli* terms, int n_terms, voi
     });
 }
 
+// Reverse-sweep rewrite: a one-qubit diagonal gate D followed by an X/Y
+// gradient read and a one-qubit gate U on the same qubit. The read sees both
+// states after D, and Im <D lam| G |D phi> = Im <lam| D^dag G D |phi>, where
+// D^dag G D is again a combination of X and Y. So the read moves before D
+// with the rotated generator, and D joins U as the single matrix U D. The
+// item that held D keeps only its own read (a Z read, which D does not
+// change), or disappears if it had none. This saves one pass over the
+// registers per such pair (RZ then RY in hardware-efficient ansatze).
+static void fold_diagonals_into_reads(std::vector<PlanItem>& items)
+{
+    std::vector<PlanItem> out;
+    out.reserve(items.size());
+    for (size_t i = 0; i < items.size(); i++) {
+        PlanItem a = items[i];
+        if (i + 1 < items.size() && a.gate && a.g.kind == G_DIAG && a.g.q[1] < 0 && a.g.ctrl == 0) {
+            PlanItem& b = items[i + 1];
+            const bool xy = b.grad && (b.g.gen == GEN_X || b.g.gen == GEN_Y || b.g.gen == GEN_XY);
+            if (xy && b.gate && b.g.kind == G_DENSE1 && b.g.ctrl == 0 && b.g.q[0] == a.g.q[0]) {
+                const cd d0 = a.g.m[0], d1 = a.g.m[1];
+                // G = cx X + cy Y has off-diagonal entry g01 = cx - i cy
+                const cd c = b.g.gen == GEN_X ? cd(1.0, 0.0) : b.g.gen == GEN_Y ? cd(0.0, 1.0) : b.gcoef;
+                const cd g01 = std::conj(d0) * cd(c.real(), -c.imag()) * d1;
+                b.gcoef = cd(g01.real(), -g01.imag());
+                b.g.gen = GEN_XY;
+                // U D: column c of U times d_c
+                b.g.m[0] *= d0;
+                b.g.m[1] *= d1;
+                b.g.m[2] *= d0;
+                b.g.m[3] *= d1;
+                if (!a.grad) continue;  // nothing left of this item
+                a.gate = false;
+            }
+        }
+        out.push_back(a);
+    }
+    items.swap(out);
+}
+
 sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const sv_pauli* terms, int n_terms,
                           void* work_buf, size_t work_bytes, double* grad_out, int n_params, double* expval_out)
 {
@@ -799,6 +837,7 @@ sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const s
         }
         items.push_back(it);
     }
+    fold_diagonals_into_reads(items);
     std::vector<PlanPass> passes;
     try {
         PlanOptions o = plan_options(s->n, s->elem, 2);

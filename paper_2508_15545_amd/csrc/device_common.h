@@ -124,6 +124,35 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Cross-lane move of a double with a DPP pattern; lanes of rows left out by
+// ROW_MASK get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROW_MASK, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane
+// (uniform). Every lane must be active. Pairs, quads, half-rows and rows
+// combine through DPP lane patterns, then row sums move across rows with the
+// row broadcasts; lane 63 ends with the total.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);  // row_mirror
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0x8>(v);  // row_bcast:31 into row 3
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll

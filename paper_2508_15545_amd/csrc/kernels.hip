@@ -427,19 +427,18 @@ __global__ __launch_bounds__(kThreads) void k_block(T* __restrict__ s0, T* __res
                     acc += bit ? -im : im;
                 }
             } else {
+                // G = cx X + cy Y on bit a
                 const int a = op.a;
+                const double cx = (double)mats[op.mat].x, cy = (double)mats[op.mat].y;
                 for (int l = tid; l < nloc; l += kThreads) {
                     const int bit = (l >> a) & 1;
                     const T f = lds0[l ^ (1 << a)], m = lds1[l];
                     // conj(m) * f
                     const double re = (double)m.x * (double)f.x + (double)m.y * (double)f.y;
                     const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
-                    if (op.gen == GEN_X) {
-                        acc += im;
-                    } else {
-                        // (Y phi)_l = (bit ? i : -i) phi_{l^a}; Im(conj(m) * (+-i) f) = +-Re(conj(m) f)
-                        acc += bit ? re : -re;
-                    }
+                    // X: (X phi)_l = phi_{l^a}; Y: (Y phi)_l = (bit ? i : -i) phi_{l^a},
+                    // and Im(conj(m) * (+-i) f) = +-Re(conj(m) f)
+                    acc += cx * im + cy * (bit ? re : -re);
                 }
             }
             const double t = block_sum(acc, red);

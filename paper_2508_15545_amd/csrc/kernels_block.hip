@@ -254,10 +254,10 @@ __device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typen
     }
 }
 
-// Im <lambda|G|phi> contributions of the thread's registers for G = X or Y
-// on window bit J (v[0] = phi, v[1] = lambda).
+// Im <lambda|G|phi> contributions of the thread's registers for
+// G = cx X + cy Y on window bit J (v[0] = phi, v[1] = lambda).
 template <typename T, int RB, int J>
-__device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], int gen)
+__device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double cx, double cy)
 {
     double acc = 0;
 #pragma unroll
@@ -268,7 +268,7 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], int gen)
         const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
         const bool bit = (k >> J) & 1;
         // X: Im(conj(m) f); Y: (Y phi)_l = (bit ? i : -i) phi_{l ^ J}
-        acc += gen == GEN_X ? im : (bit ? re : -re);
+        acc += cx * im + cy * (bit ? re : -re);
     }
     return acc;
 }
@@ -517,15 +517,15 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                         const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
                         acc += bit ? -im : im;
                     }
-                    acc = wave_sum(acc);
+                    acc = wave_total(acc);
                     if (lane == 0) red[op.slot * 8 + wave] = acc;
                 }
                 break;
             }
 #define F_G(J)                                                   \
     if constexpr (NS == 2) {                                     \
-        double acc = reg_grad_xy<T, RB, J>(v, op.gen);           \
-        acc = wave_sum(acc);                                     \
+        double acc = reg_grad_xy<T, RB, J>(v, (double)mats[cur.mat].x, (double)mats[cur.mat].y); \
+        acc = wave_total(acc);                                     \
         if (lane == 0) red[op.slot * 8 + wave] = acc;            \
     }
                 QV_ALL1(RC_GXY, F_G)

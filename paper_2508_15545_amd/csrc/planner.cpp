@@ -55,9 +55,12 @@ struct ItemBits {
 
 ItemBits bits_of(const PlanItem& it)
 {
-    ItemBits b{dense_bits(it.g), diag_bits(it.g), 0, 1};
-    if (it.g.kind == G_DENSE1 && it.g.ctrl && !(it.g.ctrl & (it.g.ctrl - 1))) b.want = it.g.ctrl;
-    if (it.g.kind == G_DIAG && it.g.q[1] >= 0 && !it.g.ctrl) b.want = (1ull << it.g.q[0]) | (1ull << it.g.q[1]);
+    ItemBits b{0, 0, 0, 0};
+    if (it.gate) {
+        b = ItemBits{dense_bits(it.g), diag_bits(it.g), 0, 1};
+        if (it.g.kind == G_DENSE1 && it.g.ctrl && !(it.g.ctrl & (it.g.ctrl - 1))) b.want = it.g.ctrl;
+        if (it.g.kind == G_DIAG && it.g.q[1] >= 0 && !it.g.ctrl) b.want = (1ull << it.g.q[0]) | (1ull << it.g.q[1]);
+    }
     if (it.grad) {
         b.n_ops++;
         if (it.g.gen == GEN_Z) b.diag |= 1ull << it.g.q[0];
@@ -915,15 +918,23 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             if (it.grad) {
                 TileOp t{};
                 t.kind = T_GRAD;
-                t.gen = g.gen;
                 t.a = pos_of[g.q[0]];
                 t.oa = g.q[0];
                 t.c = -1;
                 t.oc = -1;
                 t.slot = it.grad_slot;
                 t.mat = 0;
+                if (g.gen == GEN_Z) {
+                    t.gen = GEN_Z;
+                } else {
+                    // X, Y and rotated reads share one form: cx X + cy Y
+                    t.gen = GEN_XY;
+                    t.mat = (int32_t)pp.mats.size();
+                    pp.mats.push_back(g.gen == GEN_X ? cd(1.0, 0.0) : g.gen == GEN_Y ? cd(0.0, 1.0) : it.gcoef);
+                }
                 pp.ops.push_back(t);
             }
+            if (!it.gate) continue;
             TileOp t{};
             t.kind = g.kind == G_DENSE1 ? T_DENSE1 : g.kind == G_DENSE2 ? T_DENSE2 : T_DIAG;
             t.lctrl = local_mask(g.ctrl);

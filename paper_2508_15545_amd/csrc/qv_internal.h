@@ -27,7 +27,9 @@ enum GateKind : int32_t {
 };
 
 // Generator of a trainable gate exp(-i theta G / 2).
-enum GenKind : int32_t { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3 };
+// Generators of parametric gates; GEN_XY is a read of cx X + cy Y with the
+// coefficients (cx, cy) given next to it (a rotated X/Y generator).
+enum GenKind : int32_t { GEN_NONE = 0, GEN_X = 1, GEN_Y = 2, GEN_Z = 3, GEN_XY = 4 };
 
 struct HostGate {
     int32_t kind = G_DENSE1;
@@ -75,7 +77,7 @@ struct TileOp {
     int32_t a, c;      // local positions (-1: not local)
     int32_t oa, oc;    // global qubits for non-local diagonal bits (-1: none)
     uint32_t lctrl;    // control bits inside the block (local positions)
-    int32_t gen;       // T_GRAD: GEN_X / GEN_Y / GEN_Z
+    int32_t gen;       // T_GRAD: GEN_Z, or GEN_XY with (cx, cy) at mats[mat]
     int32_t slot;      // T_GRAD: partial row
     int32_t j0, j1;    // register-window bits of a / c (register kernel; j0 < j1)
     int32_t cnt;       // T_PHASE: number of thread terms (a multiple of 4)
@@ -210,8 +212,10 @@ struct PlanOptions {
 // generator (adjoint sweep: the read happens before the gate is applied).
 struct PlanItem {
     HostGate g;
+    bool gate = true;      // false: only the gradient read
     bool grad = false;
     int32_t grad_slot = -1;
+    cd gcoef = cd(0.0);    // g.gen == GEN_XY: the read is of real(gcoef) X + imag(gcoef) Y
 };
 
 std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, const PlanOptions& opt,

@@ -254,6 +254,41 @@ def test_adjoint_rx_and_shared_parameters(qv):
     np.testing.assert_allclose(g, g_o, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [7, 13])  # 7: LDS block kernel; 13: register kernel
+def test_adjoint_diagonal_before_rotation_reads(qv, n, dtype):
+    """Rotations directly followed by one-qubit diagonal gates on the same
+    qubit (RX then T, RY then RZ, RX then P then S, ...): in the reverse sweep
+    the diagonal gate is folded into the rotation and the X/Y read is
+    rotated. Checked against the oracle's plain adjoint."""
+    print(f"adjoint folds n={n} dtype={dtype}", flush=True)
+    rng = C.rng_for(21)
+    circ = [C.gate("u3", q, params=tuple(float(x) for x in rng.uniform(0, 6, 3))) for q in range(n)]
+    k = 0
+    for layer in range(3):
+        for q in range(n):
+            rot = ("rx", "ry")[int(rng.integers(0, 2))]
+            circ.append(C.gate(rot, q, params=(float(rng.uniform(-3, 3)),), param_index=k))
+            k += 1
+            for _ in range(int(rng.integers(0, 3))):
+                d = ("t", "s", "z", "p", "rz", "sdg")[int(rng.integers(0, 6))]
+                if d in ("p", "rz"):
+                    pi = k if d == "rz" else -1
+                    circ.append(C.gate(d, q, params=(float(rng.uniform(-3, 3)),), param_index=pi))
+                    k += 1 if d == "rz" else 0
+                else:
+                    circ.append(C.gate(d, q))
+        for q in range(layer % 2, n - 1, 2):
+            circ.append(C.gate("cz" if layer % 2 else "cx", q, q + 1))
+    terms = C.random_pauli_sum(n, 12, 5)
+    f_o, g_o = oracle.adjoint_grad(circ, n, terms, k)
+    st = qv.State(n, dtype).set_basis(0).apply(circ)
+    f, g = st.adjoint_grad(circ, terms, k)
+    tol = 1e-11 if dtype == torch.complex128 else 1e-4
+    assert abs(f - f_o) <= tol
+    assert np.max(np.abs(g - g_o)) <= tol
+
+
 def test_config_20q_hea_adjoint_vs_oracle_fd_and_shift(qv):
     """20 qubits, 10 layers, 400 parameters; complex128."""
     n, layers = 20, 10
