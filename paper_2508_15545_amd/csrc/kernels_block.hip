@@ -552,17 +552,28 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         }
     }
 
+    // Store mapping (the last stage's, when its lanes keep the 128-byte runs
+    // together, else the load mapping).
+    const StageHdr& so = hdr->out;
     if (hdr->final_wave_local != XCH_NONE) {
-        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, tl_nat, hdr->nat.woff, hdr->final_wave_local == XCH_WAVE);
+        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, thread_part(so.tpos, tb, tid), so.woff,
+                            hdr->final_wave_local == XCH_WAVE);
     }
+    {
+        uint64_t go = base;
+        for (int i = 0; i < tb; i++) go |= (uint64_t)((tid >> i) & 1) << hdr->local_q[so.tpos[i]];
+        int qo[RB];
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        uint64_t g = gt;
+        for (int j = 0; j < RB; j++) qo[j] = hdr->local_q[so.w[j]];
 #pragma unroll
-        for (int j = 0; j < RB; j++)
-            if ((k >> j) & 1) g |= 1ull << qr[j];
-        st_nt(s0 + g, v[0][k]);
-        if (NS == 2) st_nt(s1 + g, v[NS - 1][k]);
+        for (int k = 0; k < R; k++) {
+            uint64_t g = go;
+#pragma unroll
+            for (int j = 0; j < RB; j++)
+                if ((k >> j) & 1) g |= 1ull << qo[j];
+            st_nt(s0 + g, v[0][k]);
+            if (NS == 2) st_nt(s1 + g, v[NS - 1][k]);
+        }
     }
 
     if constexpr (NS == 2) {

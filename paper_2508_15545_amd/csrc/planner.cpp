@@ -159,7 +159,7 @@ void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int elem)
     }
 }
 
-uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer)
+uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer, int coal)
 {
     uint32_t P = 0;
     for (int k = 0; k < wb; k++) {
@@ -168,7 +168,7 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
             if ((exclude | P) & (1u << p)) continue;
             if (best < 0) { best = p; continue; }
             const bool pp = prefer & (1u << p), pb = prefer & (1u << best);
-            const bool low_p = p < 3, low_b = best < 3;  // keep the contiguous qubits on lanes
+            const bool low_p = p < coal, low_b = best < coal;  // keep the contiguous qubits on lanes
             if (low_p != low_b) { if (low_b) best = p; continue; }
             if (use[p] < use[best] || (use[p] == use[best] && pp && !pb)) best = p;
         }
@@ -181,6 +181,10 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
 void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
 {
     const int tb = b - r;
+    // lanes 0..coal-1 on the lowest positions make each load/store
+    // instruction a set of whole 128-byte runs
+    const int coal = elem == 16 ? 3 : 4;
+    const uint32_t coal_mask = (1u << coal) - 1;
     const int wb = (tb > 6 && wave_mode > 0) ? tb - 6 : 0;
     const bool wave_ok = tb <= 6 || wb > 0;  // one wave per block, or wave positions kept apart
     std::vector<TileOp>& ops = pp.ops;
@@ -192,7 +196,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
 
     // load/store mapping: the default wave bits sit just above the lanes
     const uint32_t default_P = wb ? (((1u << wb) - 1) << (tb - wb)) : 0;
-    uint32_t P = wave_mode == 2 ? pick_wave_positions(use, b, wb, 0, default_P) : default_P;
+    uint32_t P = wave_mode == 2 ? pick_wave_positions(use, b, wb, 0, default_P, coal) : default_P;
     uint32_t natural = 0;
     for (int p = b - 1, c = 0; p >= 0 && c < r; p--)
         if (!(P & (1u << p))) {
@@ -208,12 +212,12 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
     out.reserve(ops.size());
     pp.stages.clear();
     size_t first = 0;
-    bool first_stage = true;
     uint32_t prev_W = natural;
+    std::vector<uint32_t> stage_P;
     while (true) {
         while (first < ops.size() && done[first]) first++;
         if (first >= ops.size()) break;
-        uint32_t W = first_stage ? natural : 0;
+        uint32_t W = 0;
         uint32_t bd = 0, bg = 0;
         std::vector<size_t> taken;
         for (size_t i = first; i < ops.size(); i++) {
@@ -232,12 +236,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
                 bg |= dg[i];
             }
         }
-        if (taken.empty()) {
-            if (!first_stage) throw std::runtime_error("stage planner made no progress");
-            first_stage = false;
-            continue;
-        }
-        first_stage = false;
+        if (taken.empty()) throw std::runtime_error("stage planner made no progress");
         for (size_t i : taken)
             for (int p = 0; p < b; p++) use[p] -= (dn[i] >> p) & 1;
         // leftover window slots: controls of the stage's CNOTs first (a CNOT
@@ -255,12 +254,13 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
         for (int p = 0; p < b && popc(W) < r; p++) W |= 1u << p;
         StageHdr st{};
         const uint32_t P_prev = P, W_prev = prev_W;
-        if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat);  // an op needs a wave position
+        if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat, coal);  // an op needs a wave position
         set_mapping(st, b, W, P, r, elem);
         // exchange into this mapping: none if it is unchanged, within waves
         // if the wave positions stay, else across the workgroup
         st.wave_local = (W == W_prev && P == P_prev) ? XCH_NONE : (P == P_prev && wave_ok ? XCH_WAVE : XCH_BLOCK);
         prev_W = W;
+        stage_P.push_back(P);
         st.op_begin = (int32_t)out.size();
         st.n_ops = (int32_t)taken.size();
         for (size_t i : taken) {
@@ -288,8 +288,31 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
         }
         pp.stages.push_back(st);
     }
-    pp.hdr.final_wave_local =
-        (prev_W == natural && P == P_nat) ? XCH_NONE : (P == P_nat && wave_ok ? XCH_WAVE : XCH_BLOCK);
+    // Load straight into the first stage's mapping, and store straight from
+    // the last one, when its lanes keep the 128-byte runs together;
+    // otherwise through the natural mapping.
+    auto whole_runs = [&](const StageHdr& m) {
+        for (int i = 0; i < coal; i++)
+            if (m.tpos[i] != i) return false;
+        return true;
+    };
+    uint32_t P_load = P_nat;
+    if (!pp.stages.empty() && whole_runs(pp.stages.front())) {
+        pp.hdr.nat = pp.stages.front();
+        pp.stages.front().wave_local = XCH_NONE;
+        P_load = stage_P.front();
+    }
+    pp.hdr.nat.wave_local = XCH_NONE;
+    if (!pp.stages.empty() && whole_runs(pp.stages.back())) {
+        pp.hdr.out = pp.stages.back();
+        pp.hdr.final_wave_local = XCH_NONE;
+    } else {
+        pp.hdr.out = pp.hdr.nat;
+        const bool same = pp.stages.empty() || (prev_W == pp.hdr.nat.wmask && P == P_load);
+        pp.hdr.final_wave_local = same ? XCH_NONE : (P == P_load && wave_ok ? XCH_WAVE : XCH_BLOCK);
+    }
+    pp.hdr.out.wave_local = XCH_NONE;
+    (void)coal_mask;
     ops.swap(out);
     pp.hdr.n_stages = (int32_t)pp.stages.size();
 }

@@ -172,8 +172,9 @@ struct PassHdr {
     int32_t stage_begin;
     int32_t n_grad;     // gradient reads in this pass
     int32_t pad;
-    StageHdr nat;       // register kernel: the load/store mapping
-    int32_t final_wave_local;  // exchange back to `nat` before the store (XchKind)
+    StageHdr nat;       // register kernel: the load mapping
+    StageHdr out;       // register kernel: the store mapping
+    int32_t final_wave_local;  // exchange into `out` before the store (XchKind)
     int32_t pad3;
 };
 
