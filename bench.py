@@ -45,6 +45,36 @@ import circuits as C  # noqa: E402
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+# The block kernel's HBM traffic per launch is read from the committed
+# rocprofv3 summary, and only while the kernel sources still hash to what
+# was profiled (otherwise the figure no longer describes this kernel).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_block_reg_29q_c128_bench.md")
+KERNEL_SOURCES = ["kernels_block.hip", "device_common.h", "qv_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_15545_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(n: int, dtype: str):
+    """Counter bytes per block-pass launch for the profiled workload, or None."""
+    if n != 29 or dtype != "c128" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if line.startswith("traffic-record:"):
+                rec = dict(kv.split("=", 1) for kv in line.split(":", 1)[1].split())
+    if rec.get("source-sha256") != kernel_source_hash():
+        return None
+    return float(rec["bytes-per-launch"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -319,7 +349,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": profiled_traffic(n, args.dtype) if dominant == "block" else None,
             "launches": launches,
             "avg_launch_ms": avg_s * 1e3,
             "bytes_per_launch": per_launch,
