@@ -463,30 +463,27 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 // angle(k) = A + sum_j k_j eff[j] + (window-only part, tabulated
                 // as unit complex numbers at mats[cur.mat + k]); A and eff[j]
                 // depend on the thread's bits (terms padded to groups of 4)
-                double A = 0, eff[RB];
+                const PhaseHead& ph = *reinterpret_cast<const PhaseHead*>(phase + op.aux);
+                const PhaseTerm* pt = phase + op.aux + 1;
+                const uint32_t utid = (uint32_t)tid;
+                auto sum_terms = [&](int cnt) -> double {
+                    double acc = 0;
+                    for (int t = 0; t < cnt; t += 4) {
 #pragma unroll
-                for (int j = 0; j < RB; j++) eff[j] = 0;
-                const PhaseTerm* pt = phase + op.aux;
-                const int cnt = op.cnt;
-                for (int t = 0; t < cnt; t += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const PhaseTerm term = pt[t + u];
-                        auto bitval = [&](int p) -> int {
-                            return p < 64 ? (int)((cur_tl >> p) & 1u) : (int)((base >> (p - 64)) & 1ull);
-                        };
-                        if (term.kind == PH_THREAD) {
-                            int bv = bitval(term.p1);
-                            if (term.p2 >= 0) bv &= bitval(term.p2);
-                            A += bv ? term.th : 0.0;
-                        } else if (term.kind == PH_MIXED) {
-                            const double x = bitval(term.p1) ? term.th : 0.0;
-#pragma unroll
-                            for (int j = 0; j < RB; j++)
-                                if (j == term.j) eff[j] += x;
+                        for (int u = 0; u < 4; u++) {
+                            const PhaseTerm term = pt[t + u];
+                            // the block part of the condition is uniform
+                            const double th = (base & term.omask) == term.omask ? term.th : 0.0;
+                            acc += (utid & term.tmask) == term.tmask ? th : 0.0;
                         }
                     }
-                }
+                    pt += cnt;
+                    return acc;
+                };
+                const double A = sum_terms(ph.count[0]);
+                double eff[RB];
+#pragma unroll
+                for (int j = 0; j < RB; j++) eff[j] = sum_terms(ph.count[1 + j]);
                 // e^{2 pi i angle(k)} as products of RB + 1 unit factors
                 T f[R];
                 f[0] = cis_turns<T>(A);

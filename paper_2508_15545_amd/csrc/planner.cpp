@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <stdexcept>
 #include <utility>
@@ -744,7 +745,21 @@ TileOp make_phase(const std::vector<TileOp>& run, const StageHdr& st, int r, Pla
     // window-only part (constant, window-linear, window-quadratic terms) as a
     // table of 2^r unit complex numbers, one per register
     std::vector<double> wang(1u << r, 0.0);
-    t.aux = (int32_t)pp.phase.size();
+    // the rest as mask records: for A (target 0) and for each window bit's
+    // coefficient (target 1 + j)
+    std::vector<std::vector<PhaseTerm>> groups(r + 1);
+    auto add_bit = [&](PhaseTerm& pt, int p) {
+        if (p >= 64) {
+            pt.omask |= 1ull << (p - 64);
+            return;
+        }
+        for (int i = 0; i < pp.hdr.b - r; i++)
+            if (st.tpos[i] == p) {
+                pt.tmask |= 1u << i;
+                return;
+            }
+        throw std::runtime_error("phase term on a position that is neither thread nor window");
+    };
     for (const auto& kv : acc) {
         double th = kv.second - std::nearbyint(kv.second);  // angles are periodic in turns
         if (th == 0.0) continue;
@@ -759,22 +774,23 @@ TileOp make_phase(const std::vector<TileOp>& run, const StageHdr& st, int r, Pla
             continue;
         }
         PhaseTerm pt{};
-        pt.kind = kind;
-        pt.j = kv.first[1];
-        pt.j2 = kv.first[2];
-        pt.p1 = kv.first[3];
-        pt.p2 = kv.first[4];
         pt.th = th;
-        pp.phase.push_back(pt);
+        add_bit(pt, kv.first[3]);
+        if (kind == PH_THREAD && kv.first[4] >= 0) add_bit(pt, kv.first[4]);
+        groups[kind == PH_THREAD ? 0 : 1 + kv.first[1]].push_back(pt);
     }
-    while ((pp.phase.size() - t.aux) % 4) {
-        PhaseTerm pad{};
-        pad.kind = PH_CONST;
-        pad.j = pad.j2 = pad.p1 = pad.p2 = -1;
-        pad.th = 0.0;
-        pp.phase.push_back(pad);
+    PhaseHead head{};
+    t.aux = (int32_t)pp.phase.size();
+    pp.phase.push_back(PhaseTerm{});  // the head, filled below
+    int total = 0;
+    for (int g = 0; g <= r; g++) {
+        while (groups[g].size() % 4) groups[g].push_back(PhaseTerm{});  // th = 0: adds nothing
+        head.count[g] = (int32_t)groups[g].size();
+        total += head.count[g];
+        pp.phase.insert(pp.phase.end(), groups[g].begin(), groups[g].end());
     }
-    t.cnt = (int32_t)(pp.phase.size() - t.aux);
+    std::memcpy(&pp.phase[t.aux], &head, sizeof(head));
+    t.cnt = total;
     t.mat = (int32_t)pp.mats.size();
     for (int k = 0; k < (1 << r); k++) {
         const double a = wang[k] - std::nearbyint(wang[k]);

@@ -103,12 +103,12 @@ enum RegCode : int32_t {
     RC_GXY = 200,   // + j0: gradient read, G = X or Y on window bit j0
 };
 
-// One term of a phase polynomial, angles in turns (1 = 2 pi). The phase of
-// an amplitude is the sum of its terms; bit(p) is the amplitude's bit at
-// local position p (p < 64) or at global qubit p - 64 (outside the block).
-// The register kernel gets the terms that involve thread or outer bits
-// (PH_THREAD, PH_MIXED; PH_CONST with th = 0 pads to groups of 4); the
-// window-only terms are tabulated per register.
+// Terms of a phase polynomial, angles in turns (1 = 2 pi). The phase of an
+// amplitude is the sum of its terms; bit(p) is the amplitude's bit at local
+// position p (p < 64) or at global qubit p - 64 (outside the block). The
+// planner sorts them by the bits they involve (PhaseKind, host side only):
+// the window-only part goes into a per-register table, the rest into
+// PhaseTerm records for the register kernel.
 enum PhaseKind : int32_t {
     PH_THREAD = 0,  // A += th * bit(p1) * bit(p2) (p2 < 0: linear); p1, p2 outside the window
     PH_MIXED = 1,   // eff[j] += th * bit(p1): window bit j times a bit outside the window
@@ -116,13 +116,24 @@ enum PhaseKind : int32_t {
     PH_WQUAD = 3,   // qq[j][j2] += th: window bits j < j2
     PH_CONST = 4,   // A += th
 };
+
+// A thread-dependent phase term of a T_PHASE op: it adds th (turns) when the
+// thread index covers tmask (thread bit i = bit i of the thread index) and
+// the block's global base index covers omask.
 struct PhaseTerm {
-    int32_t kind;
-    int32_t j, j2;
-    int32_t p1, p2;
-    int32_t pad;
+    uint64_t omask;
+    uint32_t tmask;
+    uint32_t pad;
     double th;
+    double pad2;
 };
+// First record of a T_PHASE op's range: the number of terms for A (the
+// per-thread constant part) and for each window bit j's coefficient, in
+// that order; each group is padded to a multiple of 4 with zero terms.
+struct PhaseHead {
+    int32_t count[8];  // [0]: A, [1 + j]: window bit j
+};
+static_assert(sizeof(PhaseHead) == sizeof(PhaseTerm), "phase records share one array");
 
 // A stage of a register-resident block pass: the amplitudes whose local
 // positions are w[0..r) are held by one thread (register bit j <-> position
