@@ -134,6 +134,32 @@ def test_plan_fuses_bench_circuits():
     assert rc == B.SV_OK and st.n_passes < 40
 
 
+@pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64])
+def test_planner_handles_benchmark_and_random_circuits(dtype):
+    """The planner raises on an internal inconsistency (an op outside its
+    stage's window, a phase term on an unmapped position, no progress).
+    Plans for the benchmark circuits, their inverses, the 33-qubit circuit,
+    the ansatz and random circuits over every op must all succeed."""
+    def inverse(circ):
+        out = []
+        for g in reversed(circ):
+            if g.op == "u3":
+                th, ph, la = g.params
+                out.append(C.gate("u3", *g.qubits, params=(-th, -la, -ph)))
+            elif g.op in ("rx", "ry", "rz", "p", "cp"):
+                out.append(C.gate(g.op, *g.qubits, params=(-g.params[0],)))
+            else:
+                out.append(g)
+        return out
+    cases = [(29, C.random_u3_layers(29, 40, 0)), (29, inverse(C.random_u3_layers(29, 40, 0))),
+             (29, inverse(C.qft(29))), (33, C.random_u3_layers(33, 30, 0, "cz")),
+             (24, C.hea(24, 20, C.hea_params(24, 20, 0)))]
+    cases += [(18, C.random_mixed_circuit(18, 500, seed)) for seed in range(8)]
+    for n, circ in cases:
+        rc, st = plan(n, circ, dtype)
+        assert rc == B.SV_OK, (n, B.lib().sv_last_error())
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "_lib", None)
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
