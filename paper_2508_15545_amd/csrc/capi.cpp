@@ -440,6 +440,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.reg_bits = reg ? reg_bits_for((int)elem, n_states) : 0;
     const char* rb = std::getenv("QVEC_REG_BITS");  // register-window width override (3 or 4)
     if (reg && rb && (std::strcmp(rb, "3") == 0 || std::strcmp(rb, "4") == 0)) o.reg_bits = rb[0] - '0';
+    // the single-state complex128 register kernel exchanges 8-byte halves
+    o.lds_elem = (o.reg_bits > 0 && elem == 16 && n_states == 1) ? 8 : (int)elem;
     const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given (no 4x4 fusion)
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     o.prefuse = o.fuse_gates && o.reg_bits > 0;

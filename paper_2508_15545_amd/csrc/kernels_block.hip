@@ -24,10 +24,20 @@
 
 namespace qv {
 
-template <typename T>
+// The single-state complex128 kernel exchanges real and imaginary parts in
+// two rounds through a buffer of 8-byte slots (half the block's bytes), so
+// that three workgroups share a CU's LDS instead of two. Its slot map is
+// the 8-byte one, as for complex64.
+template <typename T, int NS>
+constexpr bool split_exchange() { return sizeof(T) == 16 && NS == 1; }
+
+template <typename T, int NS>
+constexpr uint32_t xch_slot_bytes() { return split_exchange<T, NS>() ? 8u : (uint32_t)sizeof(T); }
+
+template <typename T, int NS>
 __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
 {
-    return lds_slot(l, sizeof(T) == 16 ? 4 : 5);
+    return lds_slot(l, xch_slot_bytes<T, NS>() == 16 ? 4 : 5);
 }
 
 // Local index bits contributed by the thread index: thread bit i sits at
@@ -108,27 +118,50 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
                                          const uint32_t* __restrict__ wo_new, bool wave_only)
 {
     constexpr int R = 1 << RB;
+    constexpr uint32_t sb = xch_slot_bytes<T, NS>();
     unsigned char* base = reinterpret_cast<unsigned char*>(lds);
-    const uint32_t so = lds_swizzle<T>(tl_old) * (uint32_t)sizeof(T);
-    const uint32_t sn = lds_swizzle<T>(tl_new) * (uint32_t)sizeof(T);
-#pragma unroll
-    for (int k = 0; k < R; k++) {
-        const uint32_t off = so ^ wo_old[k];
-#pragma unroll
-        for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
-    }
+    const uint32_t so = lds_swizzle<T, NS>(tl_old) * sb;
+    const uint32_t sn = lds_swizzle<T, NS>(tl_new) * sb;
     // Within-wave exchanges (the wave positions did not move) read only what
     // the same wave wrote: no workgroup barrier.
-    if (wave_only) wave_lds_sync();
-    else __syncthreads();
+    auto sync = [&]() {
+        if (wave_only) wave_lds_sync();
+        else __syncthreads();
+    };
+    if constexpr (split_exchange<T, NS>()) {
+        using R8 = typename RealOf<T>::type;
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        const uint32_t off = sn ^ wo_new[k];
+        for (int part = 0; part < 2; part++) {
 #pragma unroll
-        for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
+            for (int k = 0; k < R; k++) {
+                R8* d = reinterpret_cast<R8*>(base + (so ^ wo_old[k]));
+                *d = part ? v[0][k].y : v[0][k].x;
+            }
+            sync();
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const R8 x = *reinterpret_cast<const R8*>(base + (sn ^ wo_new[k]));
+                if (part) v[0][k].y = x;
+                else v[0][k].x = x;
+            }
+            sync();
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const uint32_t off = so ^ wo_old[k];
+#pragma unroll
+            for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
+        }
+        sync();
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const uint32_t off = sn ^ wo_new[k];
+#pragma unroll
+            for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
+        }
+        sync();
     }
-    if (wave_only) wave_lds_sync();
-    else __syncthreads();
 }
 
 template <typename T, int RB, int NS, int J, bool CTRL>
@@ -284,11 +317,16 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double c
 // 128 VGPRs so that two 512-thread workgroups (LDS-limited) fill a CU.
 // With prefetch (PF) the next block's registers are live as well, and the
 // target drops to three waves per SIMD.
-template <int RB, int NS, bool PF>
-constexpr int block_waves_per_eu() { return (RB == 3 && NS == 1) ? (PF ? 3 : 4) : 1; }
+// The single-state complex128 kernel with r = 4 is held to 168 VGPRs, three
+// waves per SIMD, which its half-size exchange buffer lets the LDS hold.
+template <typename T, int RB, int NS, bool PF>
+constexpr int block_waves_per_eu()
+{
+    return (RB == 3 && NS == 1) ? (PF ? 3 : 4) : (split_exchange<T, NS>() && !PF) ? 3 : 1;
+}
 
 template <typename T, int RB, int NS, bool PF>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<RB, NS, PF>())))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<T, RB, NS, PF>())))
 void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                                                    const PassHdr* __restrict__ hdr,
                                                    const StageHdr* __restrict__ stages,
@@ -632,7 +670,7 @@ static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
 {
     const void* fn = reinterpret_cast<const void*>(&k_block_reg<T, RB, NS, PF>);
     static size_t attr_bytes = 0;
-    const size_t lds = (size_t)NS * ((size_t)1 << b) * sizeof(T);
+    const size_t lds = (size_t)NS * ((size_t)1 << b) * xch_slot_bytes<T, NS>();
     if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

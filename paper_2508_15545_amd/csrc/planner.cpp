@@ -140,7 +140,7 @@ int window_index(const StageHdr& st, int r, int pos)
 // The first window is the load window (top positions outside P), and
 // leftover window slots are filled towards it so that the last stage often
 // needs no exchange before the store.
-void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int elem)
+void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int slot_bytes)
 {
     int j = 0;
     for (int p = 0; p < b; p++)
@@ -156,7 +156,7 @@ void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int elem)
         uint32_t l = 0;
         for (int jj = 0; jj < r; jj++)
             if ((k >> jj) & 1) l |= 1u << st.w[jj];
-        st.woff[k] = lds_slot(l, elem == 16 ? 4 : 5) * (uint32_t)elem;
+        st.woff[k] = lds_slot(l, slot_bytes == 16 ? 4 : 5) * (uint32_t)slot_bytes;
     }
 }
 
@@ -179,7 +179,7 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
     return P;
 }
 
-void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
+void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
 {
     const int tb = b - r;
     // lanes 0..coal-1 on the lowest positions make each load/store
@@ -204,7 +204,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
             natural |= 1u << p;
             c++;
         }
-    set_mapping(pp.hdr.nat, b, natural, P, r, elem);
+    set_mapping(pp.hdr.nat, b, natural, P, r, xelem);
     pp.hdr.nat.wave_local = XCH_NONE;
     const uint32_t P_nat = P;
 
@@ -256,7 +256,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem)
         StageHdr st{};
         const uint32_t P_prev = P, W_prev = prev_W;
         if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat, coal);  // an op needs a wave position
-        set_mapping(st, b, W, P, r, elem);
+        set_mapping(st, b, W, P, r, xelem);
         // exchange into this mapping: none if it is unchanged, within waves
         // if the wave positions stay, else across the workgroup
         st.wave_local = (W == W_prev && P == P_prev) ? XCH_NONE : (P == P_prev && wave_ok ? XCH_WAVE : XCH_BLOCK);
@@ -1006,7 +1006,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         h.n_grad = grads;
         if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
             if (opt.fuse_gates) fuse_ops(pp);
-            plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem);
+            plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem, opt.lds_elem > 0 ? opt.lds_elem : elem);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
             set_reg_codes(pp, opt.reg_bits);

@@ -151,7 +151,9 @@ struct StageHdr {
     int32_t wave_local;  // exchange into this mapping: XCH_NONE / XCH_WAVE / XCH_BLOCK
     int32_t pad;
     // byte offset in the exchange buffer of register k's window bits
-    // (lds_slot of the window part, times the amplitude size)
+    // (lds_slot of the window part, times the slot size: 8 bytes for
+    // complex64 and for the single-state complex128 kernel, which exchanges
+    // real and imaginary parts separately; 16 bytes otherwise)
     uint32_t woff[1 << kMaxRegBits];
 };
 
@@ -215,6 +217,7 @@ struct PlanOptions {
     bool prefuse = false;         // fuse one-qubit gates into two-qubit gates over the whole circuit first
     bool want_local = false;      // also bring controls / diagonal partners into a pass when there is room
     int want_reserve = 0;         // ... keeping this many local slots free for later targets
+    int lds_elem = 0;             // bytes per exchange-buffer slot (0: the amplitude size)
     int wave_mode = 2;            // 0: workgroup-wide exchanges only; 1: fixed wave positions,
                                   // within-wave exchanges while they hold; 2: wave positions picked
                                   // from the pass's least-used positions
