@@ -453,10 +453,10 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
         if (v >= 1 && v <= kMaxLocal) o.b = std::min(n, v);
     }
     // Keep the block within what the chosen kernel can hold: the register
-    // kernel needs at most 160 KiB of LDS and at most 512 threads; the LDS
-    // kernel has a fixed 64 KiB block.
+    // kernel's exchange buffer (kRegLdsBytesPerState per state) and at most
+    // 512 threads; the LDS kernel has a fixed 64 KiB block.
     if (o.reg_bits > 0) {
-        while (o.b > 1 && ((size_t)n_states << o.b) * elem > (160u << 10)) o.b--;
+        while (o.b > 1 && ((size_t)1 << o.b) * (size_t)o.lds_elem > (size_t)kRegLdsBytesPerState) o.b--;
         while (o.b - o.reg_bits > 9) o.b--;
     } else {
         o.b = std::min(o.b, (elem == 16 ? 12 : 13) - (n_states == 2 ? 1 : 0));

@@ -335,7 +335,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                                                    int64_t gstride)
 {
     constexpr int R = 1 << RB;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[NS * kRegLdsBytesPerState];
     T* lds = reinterpret_cast<T*>(smem_raw);
     __shared__ double red[NS == 2 ? kMaxGradPerPass * 8 : 1];
 
@@ -669,13 +669,10 @@ static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
                                int64_t gs, hipStream_t st)
 {
     const void* fn = reinterpret_cast<const void*>(&k_block_reg<T, RB, NS, PF>);
-    static size_t attr_bytes = 0;
-    const size_t lds = (size_t)NS * ((size_t)1 << b) * xch_slot_bytes<T, NS>();
-    if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    // the exchange buffer is a static array of the kernel
+    if ((size_t)NS * ((size_t)1 << b) * xch_slot_bytes<T, NS>() > (size_t)NS * kRegLdsBytesPerState)
+        return hipErrorInvalidValue;
+    const size_t lds = 0;
     const uint64_t nblocks = 1ull << (n - b);
     const unsigned threads = 1u << (b - RB);
     uint64_t grid = nblocks;
@@ -690,7 +687,7 @@ static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
         static bool said = false;
         if (!said && std::getenv("QVEC_VERBOSE")) {
             std::fprintf(stderr, "k_block_reg prefetch: %d workgroups per CU, %u threads, %zu B LDS\n", per_cu,
-                         threads, lds);
+                         threads, (size_t)NS * kRegLdsBytesPerState);
             said = true;
         }
         const uint64_t g = (uint64_t)per_cu * (uint64_t)cu_count();

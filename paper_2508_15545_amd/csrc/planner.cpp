@@ -32,11 +32,11 @@ namespace qv {
 
 int default_block_qubits(int n, int elem_bytes, int n_states)
 {
-    // 2^12 amplitudes per block: 64 KiB of LDS for complex128 (two
-    // workgroups per CU, the register file allows no more), 32 KiB for
-    // complex64 (four per CU at four waves per SIMD). Measured on MI355X,
-    // occupancy beats the fewer passes of larger blocks. The adjoint carries
-    // two states and halves the complex128 block.
+    // 2^12 amplitudes per block: a 32 KiB exchange buffer (complex128
+    // exchanges real and imaginary parts in turn), three workgroups per CU
+    // for complex128 (168 VGPRs), four for complex64 (four waves per SIMD).
+    // Measured on MI355X, occupancy beats the fewer passes of larger blocks.
+    // The adjoint carries two states and halves the complex128 block.
     const int lb = n_states == 2 ? (elem_bytes == 16 ? 11 : 12) : 12;
     return std::min(n, lb);
 }

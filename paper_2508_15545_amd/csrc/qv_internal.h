@@ -170,6 +170,10 @@ constexpr uint32_t lds_slot(uint32_t l, int e)
 // (the wave positions stay, so no workgroup barrier), across the workgroup.
 enum XchKind : int32_t { XCH_NONE = 0, XCH_WAVE = 1, XCH_BLOCK = 2 };
 constexpr int kMaxGradPerPass = 128;
+// Exchange buffer of the register kernel per state carried (a static LDS
+// array, so that its addresses fold into the LDS instructions): 2^12 8-byte
+// slots, or 2^11 16-byte ones for the two-state complex128 kernel.
+constexpr int kRegLdsBytesPerState = 32768;
 
 constexpr int kMaxLocal = 16;
 constexpr int kMaxQubits = 34;
