@@ -353,23 +353,30 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
     for (int j = 0; j < kMaxRegBits; j++) wn[j] = hdr->nat.w[j];
     const uint32_t tl_nat = thread_part(hdr->nat.tpos, tb, tid);
-    uint64_t tg = 0;  // the thread's bits of the global index
-    for (int i = 0; i < tb; i++) tg |= (uint64_t)((tid >> i) & 1) << hdr->local_q[hdr->nat.tpos[i]];
-    int qr[RB];  // global qubits of the load window
+    // The thread's bits of the global index in the load mapping, and its
+    // registers' element offsets (hdr->nat_koff): the two have disjoint bits.
+    uint64_t tg = 0;
 #pragma unroll
-    for (int j = 0; j < RB; j++) qr[j] = hdr->local_q[wn[j]];
+    for (int i = 0; i < kMaxThreadBits; i++)
+        if (i < tb) tg |= (uint64_t)((tid >> i) & 1) << hdr->nat_tq[i];
+    // Block index -> global index of its first amplitude: the index's bits go
+    // to the qubits outside the block, i.e. a zero is inserted at each local
+    // qubit (ascending).
     auto block_base = [&](uint64_t blk) {
-        uint64_t bb = 0;
-        for (int j = 0; j < hdr->n_outer; j++) bb |= ((blk >> j) & 1ull) << hdr->outer_q[j];
+        uint64_t bb = blk;
+#pragma unroll
+        for (int j = 0; j < kMaxLocal; j++) {
+            if (j < b) {
+                const int q = hdr->local_q[j];
+                bb = ((bb >> q) << (q + 1)) | (bb & ((1ull << q) - 1));
+            }
+        }
         return bb;
     };
     auto load_block = [&](T (&dst)[NS][R], uint64_t g0) {
 #pragma unroll
         for (int k = 0; k < R; k++) {
-            uint64_t g = g0;
-#pragma unroll
-            for (int j = 0; j < RB; j++)
-                if ((k >> j) & 1) g |= 1ull << qr[j];
+            const uint64_t g = g0 + hdr->nat_koff[k];
             dst[0][k] = ld_nt(s0 + g);
             if (NS == 2) dst[NS - 1][k] = ld_nt(s1 + g);
         }
@@ -385,8 +392,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         // count only the loop's loads and stores.
         __builtin_amdgcn_s_waitcnt(0);
     }
-    // A grid smaller than the block count walks the blocks in strides.
-    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    // One block per workgroup; with PF, a grid smaller than the block count
+    // walks the blocks in strides.
+    auto run_block = [&](const uint64_t blk) {
     const uint64_t base = block_base(blk);
     const uint64_t gt = base | tg;
 
@@ -596,16 +604,12 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     }
     {
         uint64_t go = base;
-        for (int i = 0; i < tb; i++) go |= (uint64_t)((tid >> i) & 1) << hdr->local_q[so.tpos[i]];
-        int qo[RB];
 #pragma unroll
-        for (int j = 0; j < RB; j++) qo[j] = hdr->local_q[so.w[j]];
+        for (int i = 0; i < kMaxThreadBits; i++)
+            if (i < tb) go |= (uint64_t)((tid >> i) & 1) << hdr->out_tq[i];
 #pragma unroll
         for (int k = 0; k < R; k++) {
-            uint64_t g = go;
-#pragma unroll
-            for (int j = 0; j < RB; j++)
-                if ((k >> j) & 1) g |= 1ull << qo[j];
+            const uint64_t g = go + hdr->out_koff[k];
             st_nt(s0 + g, v[0][k]);
             if (NS == 2) st_nt(s1 + g, v[NS - 1][k]);
         }
@@ -624,23 +628,15 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
             __syncthreads();  // red[] is rewritten by the next block
         }
     }
-    }  // blocks
+    };  // run_block
+    if constexpr (PF) {
+        for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) run_block(blk);
+    } else {
+        if (blockIdx.x < nblocks) run_block(blockIdx.x);
+    }
 }
 
 #undef QV_J1_CASES
-
-// Workgroups per CU pair of slots for a persistent grid (QVEC_PERSIST=k:
-// grid = k x CUs x 2); 0 launches one workgroup per block.
-static int persist_waves()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = std::getenv("QVEC_PERSIST");
-        v = e ? std::atoi(e) : 0;
-        if (v < 0) v = 0;
-    }
-    return v;
-}
 
 // Register prefetch of the next block (QVEC_PREFETCH=1). Off by default:
 // its extra registers cost a wave per SIMD, and on the 29-qubit benchmark
@@ -692,12 +688,6 @@ static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
         }
         const uint64_t g = (uint64_t)per_cu * (uint64_t)cu_count();
         if (g < grid) grid = g;
-    } else {
-        const int wave = persist_waves();
-        if (wave > 0) {
-            const uint64_t g = (uint64_t)wave * (uint64_t)cu_count() * 2;
-            if (g < grid) grid = g;
-        }
     }
     hipLaunchKernelGGL((k_block_reg<T, RB, NS, PF>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1, d_hdr,
                        d_stages, d_ops, d_mats, d_phase, gp, gs);

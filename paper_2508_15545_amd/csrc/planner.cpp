@@ -318,6 +318,26 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
     pp.hdr.n_stages = (int32_t)pp.stages.size();
 }
 
+// Global qubit of each thread bit and element offset of each register in
+// the load and store mappings, so that the kernel forms its addresses
+// without looking up local positions.
+void set_io_offsets(PassHdr& h, int r)
+{
+    const int tb = h.b - r;
+    auto fill = [&](const StageHdr& m, int32_t* tq, uint64_t* koff) {
+        for (int i = 0; i < kMaxThreadBits; i++) tq[i] = i < tb ? h.local_q[m.tpos[i]] : 0;
+        for (int k = 0; k < (1 << kMaxRegBits); k++) {
+            uint64_t o = 0;
+            if (k < (1 << r))
+                for (int j = 0; j < r; j++)
+                    if ((k >> j) & 1) o |= 1ull << h.local_q[m.w[j]];
+            koff[k] = o;
+        }
+    };
+    fill(h.nat, h.nat_tq, h.nat_koff);
+    fill(h.out, h.out_tq, h.out_koff);
+}
+
 // Flat dispatch code of an op for the register kernel (after stages and
 // diagonal merging).
 int32_t reg_code(const TileOp& t)
@@ -1010,6 +1030,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
             set_reg_codes(pp, opt.reg_bits);
+            set_io_offsets(pp.hdr, opt.reg_bits);
         }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
         passes.push_back(std::move(pp));

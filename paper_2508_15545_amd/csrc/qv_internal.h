@@ -3,6 +3,7 @@
 #pragma once
 
 #include <complex>
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -193,7 +194,15 @@ struct PassHdr {
     StageHdr out;       // register kernel: the store mapping
     int32_t final_wave_local;  // exchange into `out` before the store (XchKind)
     int32_t pad3;
+    // register kernel, derived from nat / out and local_q by the planner:
+    // global qubit of thread bit i, and element offset of register k's
+    // window bits, in the load and in the store mapping
+    int32_t nat_tq[kMaxThreadBits];
+    int32_t out_tq[kMaxThreadBits];
+    uint64_t nat_koff[1 << kMaxRegBits];
+    uint64_t out_koff[1 << kMaxRegBits];
 };
+static_assert(offsetof(PassHdr, nat_koff) % 8 == 0, "64-bit offsets are aligned");
 
 // One launch of a plan.
 struct PlanPass {
