@@ -45,7 +45,17 @@ __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
 __device__ __forceinline__ uint32_t thread_part(const int32_t* tpos, int tb, int tid)
 {
     uint32_t tl = 0;
-    for (int i = 0; i < tb; i++) tl |= (uint32_t)((tid >> i) & 1) << tpos[i];
+    // Unrolled with a guard, so that the positions arrive in one scalar
+    // load; the opaque copy of tid keeps the bit extractions here instead of
+    // in registers held across the whole kernel.
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    int tp[kMaxThreadBits];
+#pragma unroll
+    for (int i = 0; i < kMaxThreadBits; i++) tp[i] = tpos[i];
+#pragma unroll
+    for (int i = 0; i < kMaxThreadBits; i++)
+        if (i < tb) tl |= (uint32_t)((t >> i) & 1) << tp[i];
     return tl;
 }
 
@@ -357,8 +367,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     // registers' element offsets (hdr->nat_koff): the two have disjoint bits.
     uint64_t tg = 0;
 #pragma unroll
-    for (int i = 0; i < kMaxThreadBits; i++)
+    for (int i = 0; i < kMaxThreadBits; i++) {
         if (i < tb) tg |= (uint64_t)((tid >> i) & 1) << hdr->nat_tq[i];
+    }
     // Block index -> global index of its first amplitude: the index's bits go
     // to the qubits outside the block, i.e. a zero is inserted at each local
     // qubit (ascending).
@@ -366,10 +377,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         uint64_t bb = blk;
 #pragma unroll
         for (int j = 0; j < kMaxLocal; j++) {
-            if (j < b) {
-                const int q = hdr->local_q[j];
-                bb = ((bb >> q) << (q + 1)) | (bb & ((1ull << q) - 1));
-            }
+            const int q = hdr->local_q[j] & 63;
+            const uint64_t ins = ((bb >> q) << 1 << q) | (bb & ((1ull << q) - 1));
+            bb = j < b ? ins : bb;
         }
         return bb;
     };
@@ -605,8 +615,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     {
         uint64_t go = base;
 #pragma unroll
-        for (int i = 0; i < kMaxThreadBits; i++)
+        for (int i = 0; i < kMaxThreadBits; i++) {
             if (i < tb) go |= (uint64_t)((tid >> i) & 1) << hdr->out_tq[i];
+        }
 #pragma unroll
         for (int k = 0; k < R; k++) {
             const uint64_t g = go + hdr->out_koff[k];
