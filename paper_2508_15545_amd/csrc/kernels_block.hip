@@ -498,9 +498,11 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 const bool ctrl = op.lctrl != 0;
                 const int ua = a < 0 ? (op.oa >= 0 ? (int)((base >> op.oa) & 1) : 0) : 0;
                 const int uc = c < 0 ? (op.oc >= 0 ? (int)((base >> op.oc) & 1) : 0) : 0;
+                uint32_t tlx = cur_tl;  // opaque: the indices are formed here, not held across the op loop
+                asm volatile("" : "+v"(tlx));
 #pragma unroll
                 for (int k = 0; k < R; k++) {
-                    const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
+                    const uint32_t l = tlx | window_part<RB>(k, cur_w);
                     const int ba = a >= 0 ? (int)((l >> a) & 1) : ua;
                     const int bc = c >= 0 ? (int)((l >> c) & 1) : uc;
                     const int sel = ba + 2 * bc;
@@ -562,9 +564,11 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                     double acc = 0;
                     const int a = op.a;
                     const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
+                    uint32_t tlx = cur_tl;
+                    asm volatile("" : "+v"(tlx));
 #pragma unroll
                     for (int k = 0; k < R; k++) {
-                        const uint32_t l = cur_tl | window_part<RB>(k, cur_w);
+                        const uint32_t l = tlx | window_part<RB>(k, cur_w);
                         const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
                         const T f = v[0][k], m = v[1][k];
                         const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
