@@ -121,17 +121,21 @@ __device__ __forceinline__ OpHot op_hot(const TileOp* p)
 // The slot map is linear over XOR and the thread and window parts of an
 // index have disjoint bits, so slot(tl | wl) = slot(tl) ^ slot(wl): one
 // per-thread term and one uniform term per register, the latter read from the
-// stage table (wo_old / wo_new: byte offsets, uniform scalar loads).
+// stage table (wo_new: byte offsets, uniform scalar loads). The offsets of
+// the current mapping are kept in registers from one exchange to the next.
 template <typename T, int RB, int NS>
-__device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, uint32_t tl_old,
-                                         const uint32_t* __restrict__ wo_old, uint32_t tl_new,
-                                         const uint32_t* __restrict__ wo_new, bool wave_only)
+__device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, uint32_t (&aoff)[1 << RB],
+                                         uint32_t tl_new, const uint32_t* __restrict__ wo_new, bool wave_only)
 {
+    // aoff: the registers' byte offsets in the current mapping (kept from the
+    // previous exchange); on return, those of the new mapping.
     constexpr int R = 1 << RB;
     constexpr uint32_t sb = xch_slot_bytes<T, NS>();
     unsigned char* base = reinterpret_cast<unsigned char*>(lds);
-    const uint32_t so = lds_swizzle<T, NS>(tl_old) * sb;
     const uint32_t sn = lds_swizzle<T, NS>(tl_new) * sb;
+    uint32_t noff[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) noff[k] = sn ^ wo_new[k];
     // Within-wave exchanges (the wave positions did not move) read only what
     // the same wave wrote: no workgroup barrier.
     auto sync = [&]() {
@@ -144,13 +148,13 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
         for (int part = 0; part < 2; part++) {
 #pragma unroll
             for (int k = 0; k < R; k++) {
-                R8* d = reinterpret_cast<R8*>(base + (so ^ wo_old[k]));
+                R8* d = reinterpret_cast<R8*>(base + aoff[k]);
                 *d = part ? v[0][k].y : v[0][k].x;
             }
             sync();
 #pragma unroll
             for (int k = 0; k < R; k++) {
-                const R8 x = *reinterpret_cast<const R8*>(base + (sn ^ wo_new[k]));
+                const R8 x = *reinterpret_cast<const R8*>(base + noff[k]);
                 if (part) v[0][k].y = x;
                 else v[0][k].x = x;
             }
@@ -159,19 +163,21 @@ __device__ __forceinline__ void exchange(T (&v)[NS][1 << RB], T* lds, int nloc, 
     } else {
 #pragma unroll
         for (int k = 0; k < R; k++) {
-            const uint32_t off = so ^ wo_old[k];
 #pragma unroll
-            for (int s = 0; s < NS; s++) *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + off) = v[s][k];
+            for (int s = 0; s < NS; s++)
+                *reinterpret_cast<T*>(base + (size_t)s * nloc * sizeof(T) + aoff[k]) = v[s][k];
         }
         sync();
 #pragma unroll
         for (int k = 0; k < R; k++) {
-            const uint32_t off = sn ^ wo_new[k];
 #pragma unroll
-            for (int s = 0; s < NS; s++) v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + off);
+            for (int s = 0; s < NS; s++)
+                v[s][k] = *reinterpret_cast<const T*>(base + (size_t)s * nloc * sizeof(T) + noff[k]);
         }
         sync();
     }
+#pragma unroll
+    for (int k = 0; k < R; k++) aoff[k] = noff[k];
 }
 
 template <typename T, int RB, int NS, int J, bool CTRL>
@@ -426,7 +432,12 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
     for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = wn[j];
     uint32_t cur_tl = tl_nat;
-    const uint32_t* cur_wo = hdr->nat.woff;
+    uint32_t aoff[R];  // exchange-buffer offsets of the registers in the current mapping
+    {
+        const uint32_t s_nat = lds_swizzle<T, NS>(tl_nat) * xch_slot_bytes<T, NS>();
+#pragma unroll
+        for (int k = 0; k < R; k++) aoff[k] = s_nat ^ hdr->nat.woff[k];
+    }
 
     const TileOp* po = ops + hdr->op_begin;
     const int n_stages = hdr->n_stages;
@@ -437,9 +448,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) w_new[j] = sh.w[j];
             const uint32_t tl_new = thread_part(sh.tpos, tb, tid);
-            exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, tl_new, sh.woff, sh.wave_local == XCH_WAVE);
+            exchange<T, RB, NS>(v, lds, nloc, aoff, tl_new, sh.woff, sh.wave_local == XCH_WAVE);
             cur_tl = tl_new;
-            cur_wo = sh.woff;
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
         }
@@ -613,7 +623,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     // together, else the load mapping).
     const StageHdr& so = hdr->out;
     if (hdr->final_wave_local != XCH_NONE) {
-        exchange<T, RB, NS>(v, lds, nloc, cur_tl, cur_wo, thread_part(so.tpos, tb, tid), so.woff,
+        exchange<T, RB, NS>(v, lds, nloc, aoff, thread_part(so.tpos, tb, tid), so.woff,
                             hdr->final_wave_local == XCH_WAVE);
     }
     {
