@@ -442,6 +442,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     if (reg && rb && (std::strcmp(rb, "3") == 0 || std::strcmp(rb, "4") == 0)) o.reg_bits = rb[0] - '0';
     // the single-state complex128 register kernel exchanges 8-byte halves
     o.lds_elem = (o.reg_bits > 0 && elem == 16 && n_states == 1) ? 8 : (int)elem;
+    const char* sel = std::getenv("QVEC_PASS_SELECT");  // "greedy": local sets grown in gate order only
+    if (sel && std::strcmp(sel, "greedy") == 0) o.best_gain = false;
     const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given (no 4x4 fusion)
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     o.prefuse = o.fuse_gates && o.reg_bits > 0;

@@ -897,46 +897,97 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         while (first < items.size() && done[first]) first++;
         if (first >= items.size()) break;
 
-        uint64_t S = 0;
+        uint64_t S0 = 0;
         if (b == n) {
-            S = all;
+            S0 = all;
         } else {
-            for (int q = 0; q < std::min(opt.coalesce, b); q++) S |= 1ull << q;
+            for (int q = 0; q < std::min(opt.coalesce, b); q++) S0 |= 1ull << q;
         }
-        uint64_t blk_dense = 0, blk_diag = 0;
-        std::vector<size_t> taken;
-        int ops = 0;
-        int grads = 0;
-        int scanned = 0;
-        for (size_t i = first; i < items.size() && scanned < opt.lookahead; i++) {
-            if (done[i]) continue;
-            scanned++;
-            const ItemBits& it = ib[i];
-            bool ok = !(it.dense & (blk_dense | blk_diag)) && !(it.diag & blk_dense);
-            if (ok) {
-                const uint64_t need = it.dense & ~S;
-                if (popc(S | need) > b || ops + it.n_ops > opt.max_ops ||
-                    (items[i].grad && grads >= kMaxGradPerPass))
-                    ok = false;
-                else S |= need;
-                if (ok && opt.want_local) {
-                    const uint64_t w = it.want & ~S;
-                    if (w && popc(S | w) <= b - opt.want_reserve) S |= w;
+        // In-order scan from the first pending item: an item is taken when its
+        // dense qubits are (or, with `grow`, can still be made) local and no
+        // skipped earlier item it does not commute with blocks it. Returns
+        // the number taken; fills `taken` and the final local set when given.
+        auto scan = [&](uint64_t& S, bool grow, std::vector<size_t>* taken) {
+            uint64_t blk_dense = 0, blk_diag = 0;
+            int ops = 0, grads = 0, scanned = 0, count = 0;
+            for (size_t i = first; i < items.size() && scanned < opt.lookahead; i++) {
+                if (done[i]) continue;
+                scanned++;
+                const ItemBits& it = ib[i];
+                bool ok = !(it.dense & (blk_dense | blk_diag)) && !(it.diag & blk_dense);
+                if (ok) {
+                    const uint64_t need = it.dense & ~S;
+                    if ((need && (!grow || popc(S | need) > b)) || ops + it.n_ops > opt.max_ops ||
+                        (items[i].grad && grads >= kMaxGradPerPass))
+                        ok = false;
+                    else S |= need;
+                    if (ok && grow && opt.want_local) {
+                        const uint64_t w = it.want & ~S;
+                        if (w && popc(S | w) <= b - opt.want_reserve) S |= w;
+                    }
+                }
+                if (ok) {
+                    if (taken) taken->push_back(i);
+                    count++;
+                    ops += it.n_ops;
+                    grads += items[i].grad ? 1 : 0;
+                } else {
+                    blk_dense |= it.dense;
+                    blk_diag |= it.diag;
+                    if ((blk_dense & all) == all) break;  // nothing later can be taken
                 }
             }
-            if (ok) {
-                taken.push_back(i);
-                ops += it.n_ops;
-                grads += items[i].grad ? 1 : 0;
-            } else {
-                blk_dense |= it.dense;
-                blk_diag |= it.diag;
-                if ((blk_dense & all) == all) break;  // nothing later can be taken
+            return count;
+        };
+        // Local set, first choice: grown in item order (each item's qubits join
+        // while there is room).
+        uint64_t S = S0;
+        std::vector<size_t> taken;
+        scan(S, true, &taken);
+        // Second choice: start from the first pending item's qubits and add,
+        // one candidate item at a time, the missing qubits that let the most
+        // further items in per added qubit. The pass keeps whichever set
+        // takes more items.
+        if (opt.best_gain && b < n) {
+            uint64_t S1 = S0 | ib[first].dense;
+            if (popc(S1) <= b) {
+                while (true) {
+                    uint64_t t = S1;
+                    const int base = scan(t, false, nullptr);
+                    double best = 0;
+                    uint64_t best_S = 0;
+                    int seen = 0;
+                    for (size_t i = first; i < items.size() && seen < opt.gain_candidates; i++) {
+                        if (done[i]) continue;
+                        seen++;
+                        const uint64_t need = ib[i].dense & ~S1;
+                        if (!need || popc(S1 | need) > b) continue;
+                        uint64_t u = S1 | need;
+                        const double gain = (double)(scan(u, false, nullptr) - base) / popc(need);
+                        if (gain > best) {
+                            best = gain;
+                            best_S = S1 | need;
+                        }
+                    }
+                    if (best <= 0) break;
+                    S1 = best_S;
+                }
+                std::vector<size_t> taken1;
+                uint64_t u = S1;
+                scan(u, false, &taken1);
+                if (taken1.size() >= taken.size()) {
+                    taken.swap(taken1);
+                    S = S1;
+                }
             }
         }
         if (taken.empty()) throw std::runtime_error("planner made no progress");
         for (int q = 0; q < n && popc(S) < b; q++) S |= 1ull << q;  // fill with the lowest qubits
-        for (size_t i : taken) done[i] = 1;
+        int grads = 0;
+        for (size_t i : taken) {
+            done[i] = 1;
+            grads += items[i].grad ? 1 : 0;
+        }
 
         PlanPass pp;
         const bool single = taken.size() == 1 && !items[taken[0]].grad;

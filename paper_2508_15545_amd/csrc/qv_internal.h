@@ -223,6 +223,8 @@ struct PlanOptions {
     int n_states = 1;      // 2 for the adjoint sweep (phi and lambda together)
     int max_ops = 2048;    // ops per block pass
     int lookahead = 4096;  // gates scanned when filling a pass
+    bool best_gain = true;     // also try growing each pass's local set by best gain per qubit
+    int gain_candidates = 64;  // pending items tried as additions per growth step
     bool single_gate_sweeps = true;  // a pass holding one gate uses its sweep kernel
     int reg_bits = 0;      // register-window bits r (0: no stage planning)
     bool merge_diagonals = true;  // runs of diagonal gates become phase polynomials
