@@ -531,6 +531,15 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 // angle(k) = A + sum_j k_j eff[j] + (window-only part, tabulated
                 // as unit complex numbers at mats[cur.mat + k]); A and eff[j]
                 // depend on the thread's bits (terms padded to groups of 4)
+                if (op.cnt == 0) {  // window-only: the table is the whole phase
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        const T g = mats[cur.mat + k];
+#pragma unroll
+                        for (int s = 0; s < NS; s++) v[s][k] = cmul(g, v[s][k]);
+                    }
+                    break;
+                }
                 const PhaseHead& ph = *reinterpret_cast<const PhaseHead*>(phase + op.aux);
                 const PhaseTerm* pt = phase + op.aux + 1;
                 const uint32_t utid = (uint32_t)tid;

@@ -844,7 +844,26 @@ void merge_diagonals(PlanPass& pp, int r)
                 pending_pos |= local_positions(t);
                 continue;
             }
-            if (dense_positions(t) & pending_pos) flush(si);
+            const uint32_t dp = dense_positions(t);
+            if (dp & pending_pos) {
+                // Only the pending diagonals that share a position with this op
+                // must be applied before it; the others commute with it and
+                // stay pending, so that later diagonals join them.
+                std::vector<TileOp> keep;
+                uint32_t keep_pos = 0;
+                for (size_t k = 0; k < pending.size();) {
+                    if (local_positions(pending[k]) & dp) {
+                        k++;
+                    } else {
+                        keep.push_back(pending[k]);
+                        keep_pos |= local_positions(pending[k]);
+                        pending.erase(pending.begin() + (long)k);
+                    }
+                }
+                flush(si);
+                pending.swap(keep);
+                pending_pos = keep_pos;
+            }
             out[si].push_back(t);
         }
     }
