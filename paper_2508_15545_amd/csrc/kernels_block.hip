@@ -546,12 +546,24 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 auto sum_terms = [&](int cnt) -> double {
                     double acc = 0;
                     for (int t = 0; t < cnt; t += 4) {
+                        // four records in one batch of scalar loads
+                        const uint64_t* rec = reinterpret_cast<const uint64_t*>(pt + t);
+                        uint64_t w[16];
+#pragma unroll
+                        for (int i = 0; i < 16; i++) w[i] = rec[i];
+                        // every word in hand before use: one batch of loads, no per-record waits
+#pragma unroll
+                        for (int i = 0; i < 16; i++) asm volatile("" : : "s"(w[i]));
 #pragma unroll
                         for (int u = 0; u < 4; u++) {
-                            const PhaseTerm term = pt[t + u];
-                            // the block part of the condition is uniform
-                            const double th = (base & term.omask) == term.omask ? term.th : 0.0;
-                            acc += (utid & term.tmask) == term.tmask ? th : 0.0;
+                            const uint64_t omask = w[4 * u];
+                            const uint32_t tmask = (uint32_t)w[4 * u + 1];
+                            // the block part of the condition is uniform (an
+                            // integer select, so the angle's load is not branched on)
+                            const uint64_t keep_th = (base & omask) == omask ? ~0ull : 0ull;
+                            const double th = __longlong_as_double((long long)(w[4 * u + 2] & keep_th));
+                            // acc + th or acc, exactly as an add or no add
+                            acc = fma(th, (utid & tmask) == tmask ? 1.0 : 0.0, acc);
                         }
                     }
                     pt += cnt;
