@@ -386,7 +386,7 @@ sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1
             {
                 LaunchTimer tm(s, n_states == 2 ? KF_ADJ_BLOCK : KF_BLOCK);
                 const PassHdr* h = d_hdr + off.hdr[ih] / sizeof(PassHdr);
-                if (!pp.stages.empty()) {
+                if (pp.reg_bits > 0) {  // register kernel (a pass of it may have no stages: a pure permutation)
                     HIP_TRY((launch_block_reg<T>(s0, s1, s->n, n_states, pp.reg_bits, h, d_stages, d_ops, d_mats,
                                                  d_phase, b, s->d_part, nblocks, s->stream)));
                 } else {
@@ -447,6 +447,10 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     const char* fuse = std::getenv("QVEC_FUSE");  // "0": keep gates as given (no 4x4 fusion)
     o.fuse_gates = !(fuse && std::strcmp(fuse, "0") == 0);
     o.prefuse = o.fuse_gates && o.reg_bits > 0;
+    // "1": passes may move qubits between state bits (fewer passes, but on
+    // MI355X the extra store exchanges cost more than the passes saved)
+    const char* pk = std::getenv("QVEC_PARK");
+    o.park = o.reg_bits > 0 && pk && std::strcmp(pk, "1") == 0;
     const char* wm = std::getenv("QVEC_WAVE_MODE");  // "0" | "1" | "2": see PlanOptions::wave_mode
     if (wm && wm[0] >= '0' && wm[0] <= '2' && wm[1] == 0) o.wave_mode = wm[0] - '0';
     const char* bq = std::getenv("QVEC_BLOCK_QUBITS");  // block size override (local qubits)

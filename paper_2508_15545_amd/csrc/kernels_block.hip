@@ -334,11 +334,15 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double c
 // With prefetch (PF) the next block's registers are live as well, and the
 // target drops to three waves per SIMD.
 // The single-state complex128 kernel with r = 4 is held to 168 VGPRs, three
-// waves per SIMD, which its half-size exchange buffer lets the LDS hold.
+// waves per SIMD, which its half-size exchange buffer lets the LDS hold; the
+// single-state complex64 one to 96 VGPRs, five waves per SIMD, as many as
+// its 32 KiB exchange buffers let a CU's LDS hold.
 template <typename T, int RB, int NS, bool PF>
 constexpr int block_waves_per_eu()
 {
-    return (RB == 3 && NS == 1) ? (PF ? 3 : 4) : (split_exchange<T, NS>() && !PF) ? 3 : 1;
+    return (RB == 3 && NS == 1) ? (PF ? 3 : 4)
+         : (split_exchange<T, NS>() && !PF) ? 3
+         : (sizeof(T) == 8 && NS == 1 && !PF) ? 5 : 1;
 }
 
 template <typename T, int RB, int NS, bool PF>

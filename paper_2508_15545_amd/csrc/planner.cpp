@@ -160,7 +160,10 @@ void set_mapping(StageHdr& st, int b, uint32_t W, uint32_t P, int r, int slot_by
     }
 }
 
-uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer, int coal)
+// `avoid`: positions kept off the wave bits while others are free (those
+// whose lanes make contiguous runs at the load or at the store).
+uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_t exclude, uint32_t prefer,
+                             uint32_t avoid)
 {
     uint32_t P = 0;
     for (int k = 0; k < wb; k++) {
@@ -169,7 +172,7 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
             if ((exclude | P) & (1u << p)) continue;
             if (best < 0) { best = p; continue; }
             const bool pp = prefer & (1u << p), pb = prefer & (1u << best);
-            const bool low_p = p < coal, low_b = best < coal;  // keep the contiguous qubits on lanes
+            const bool low_p = (avoid >> p) & 1u, low_b = (avoid >> best) & 1u;  // keep the run qubits on lanes
             if (low_p != low_b) { if (low_b) best = p; continue; }
             if (use[p] < use[best] || (use[p] == use[best] && pp && !pb)) best = p;
         }
@@ -179,13 +182,26 @@ uint32_t pick_wave_positions(const std::vector<int>& use, int b, int wb, uint32_
     return P;
 }
 
-void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
+// store_first (may be null): the local positions whose bits the store writes
+// to the block's lowest qubits, lowest first; null when the store writes each
+// position to the qubit it was loaded from (then they are positions 0..).
+void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem, const int* store_first,
+                 uint32_t moved_mask)
 {
     const int tb = b - r;
     // lanes 0..coal-1 on the lowest positions make each load/store
     // instruction a set of whole 128-byte runs
     const int coal = elem == 16 ? 3 : 4;
     const uint32_t coal_mask = (1u << coal) - 1;
+    int sfirst[8];
+    uint32_t store_mask = 0;
+    bool store_ident = true;
+    for (int i = 0; i < coal; i++) {
+        sfirst[i] = store_first ? store_first[i] : i;
+        store_mask |= 1u << sfirst[i];
+        store_ident = store_ident && sfirst[i] == i;
+    }
+    const uint32_t avoid = coal_mask | store_mask | moved_mask;
     const int wb = (tb > 6 && wave_mode > 0) ? tb - 6 : 0;
     const bool wave_ok = tb <= 6 || wb > 0;  // one wave per block, or wave positions kept apart
     std::vector<TileOp>& ops = pp.ops;
@@ -197,7 +213,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
 
     // load/store mapping: the default wave bits sit just above the lanes
     const uint32_t default_P = wb ? (((1u << wb) - 1) << (tb - wb)) : 0;
-    uint32_t P = wave_mode == 2 ? pick_wave_positions(use, b, wb, 0, default_P, coal) : default_P;
+    uint32_t P = wave_mode == 2 ? pick_wave_positions(use, b, wb, 0, default_P, avoid) : default_P;
     uint32_t natural = 0;
     for (int p = b - 1, c = 0; p >= 0 && c < r; p--)
         if (!(P & (1u << p))) {
@@ -255,7 +271,7 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
         for (int p = 0; p < b && popc(W) < r; p++) W |= 1u << p;
         StageHdr st{};
         const uint32_t P_prev = P, W_prev = prev_W;
-        if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat, coal);  // an op needs a wave position
+        if (W & P) P = pick_wave_positions(use, b, wb, W, P_nat, avoid);  // an op needs a wave position
         set_mapping(st, b, W, P, r, xelem);
         // exchange into this mapping: none if it is unchanged, within waves
         // if the wave positions stay, else across the workgroup
@@ -292,25 +308,66 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
     // Load straight into the first stage's mapping, and store straight from
     // the last one, when its lanes keep the 128-byte runs together;
     // otherwise through the natural mapping.
-    auto whole_runs = [&](const StageHdr& m) {
+    auto whole_runs = [&](const StageHdr& m, const int* first) {
         for (int i = 0; i < coal; i++)
-            if (m.tpos[i] != i) return false;
+            if (m.tpos[i] != first[i]) return false;
         return true;
     };
+    const int ident[8] = {0, 1, 2, 3, 4, 5, 6, 7};
     uint32_t P_load = P_nat;
-    if (!pp.stages.empty() && whole_runs(pp.stages.front())) {
+    if (!pp.stages.empty() && whole_runs(pp.stages.front(), ident)) {
         pp.hdr.nat = pp.stages.front();
         pp.stages.front().wave_local = XCH_NONE;
         P_load = stage_P.front();
     }
     pp.hdr.nat.wave_local = XCH_NONE;
-    if (!pp.stages.empty() && whole_runs(pp.stages.back())) {
+    if (!pp.stages.empty() && whole_runs(pp.stages.back(), sfirst)) {
         pp.hdr.out = pp.stages.back();
         pp.hdr.final_wave_local = XCH_NONE;
-    } else {
+    } else if (store_ident) {
         pp.hdr.out = pp.hdr.nat;
         const bool same = pp.stages.empty() || (prev_W == pp.hdr.nat.wmask && P == P_load);
         pp.hdr.final_wave_local = same ? XCH_NONE : (P == P_load && wave_ok ? XCH_WAVE : XCH_BLOCK);
+    } else {
+        // A store that moves qubits: lanes 0..coal-1 on the positions written
+        // to the lowest qubits, the window on the top positions left over.
+        const uint32_t P_cur = pp.stages.empty() ? P_load : P;
+        const uint32_t P_st = (P_cur & store_mask) ? pick_wave_positions(use, b, wb, store_mask, P_cur, avoid) : P_cur;
+        uint32_t W_st = 0;
+        for (int p = b - 1, c = 0; p >= 0 && c < r; p--)
+            if (!((P_st | store_mask) & (1u << p))) {
+                W_st |= 1u << p;
+                c++;
+            }
+        StageHdr& o = pp.hdr.out;
+        o = StageHdr{};
+        set_mapping(o, b, W_st, P_st, r, xelem);
+        // lanes first: the run positions in store order, then the other free positions
+        int i = 0;
+        for (int k = 0; k < coal; k++) o.tpos[i++] = sfirst[k];
+        for (int p = 0; p < b; p++)
+            if (!((W_st | P_st | store_mask) & (1u << p))) o.tpos[i++] = p;
+        for (int p = 0; p < b; p++)
+            if (P_st & (1u << p)) o.tpos[i++] = p;
+        if (i != tb) throw std::runtime_error("store mapping does not cover the thread bits");
+        const StageHdr& last = pp.stages.empty() ? pp.hdr.nat : pp.stages.back();
+        bool same = last.wmask == o.wmask;
+        for (int k = 0; k < tb && same; k++) same = last.tpos[k] == o.tpos[k];
+        pp.hdr.final_wave_local = same ? XCH_NONE : (P_st == P_cur && wave_ok ? XCH_WAVE : XCH_BLOCK);
+    }
+    // A store that moves qubits writes an amplitude to another address of the
+    // block than the one it was loaded from. Without a workgroup-wide exchange
+    // in the pass each wave keeps its amplitudes from load to store, and its
+    // stores stay on the addresses it loaded only if the moved positions
+    // avoid the wave positions; otherwise a wave could overwrite what another
+    // wave has not loaded yet, and the final exchange becomes workgroup-wide
+    // (its barrier separates every wave's loads from every wave's stores).
+    if (store_first) {
+        bool barrier = pp.hdr.final_wave_local == XCH_BLOCK;
+        for (const StageHdr& st : pp.stages) barrier = barrier || st.wave_local == XCH_BLOCK;
+        uint32_t wave_pos = 0;
+        for (int i = 6; i < tb; i++) wave_pos |= 1u << pp.hdr.out.tpos[i];
+        if (!barrier && (moved_mask & wave_pos)) pp.hdr.final_wave_local = XCH_BLOCK;
     }
     pp.hdr.out.wave_local = XCH_NONE;
     (void)coal_mask;
@@ -321,21 +378,23 @@ void plan_stages(PlanPass& pp, int b, int r, int wave_mode, int elem, int xelem)
 // Global qubit of each thread bit and element offset of each register in
 // the load and store mappings, so that the kernel forms its addresses
 // without looking up local positions.
-void set_io_offsets(PassHdr& h, int r)
+// store_q (may be null): the qubit each local position is written to (a
+// permutation of local_q); null: the qubit it was loaded from.
+void set_io_offsets(PassHdr& h, int r, const int32_t* store_q)
 {
     const int tb = h.b - r;
-    auto fill = [&](const StageHdr& m, int32_t* tq, uint64_t* koff) {
-        for (int i = 0; i < kMaxThreadBits; i++) tq[i] = i < tb ? h.local_q[m.tpos[i]] : 0;
+    auto fill = [&](const StageHdr& m, const int32_t* q_of, int32_t* tq, uint64_t* koff) {
+        for (int i = 0; i < kMaxThreadBits; i++) tq[i] = i < tb ? q_of[m.tpos[i]] : 0;
         for (int k = 0; k < (1 << kMaxRegBits); k++) {
             uint64_t o = 0;
             if (k < (1 << r))
                 for (int j = 0; j < r; j++)
-                    if ((k >> j) & 1) o |= 1ull << h.local_q[m.w[j]];
+                    if ((k >> j) & 1) o |= 1ull << q_of[m.w[j]];
             koff[k] = o;
         }
     };
-    fill(h.nat, h.nat_tq, h.nat_koff);
-    fill(h.out, h.out_tq, h.out_koff);
+    fill(h.nat, h.local_q, h.nat_tq, h.nat_koff);
+    fill(h.out, store_q ? store_q : h.local_q, h.out_tq, h.out_koff);
 }
 
 // Flat dispatch code of an op for the register kernel (after stages and
@@ -880,6 +939,35 @@ void merge_diagonals(PlanPass& pp, int r)
 
 }  // namespace
 
+// Every mapping of a staged pass places each local position exactly once,
+// and the store writes the block's own qubits (a permutation of local_q), so
+// that every load and store address stays inside the block.
+void check_mappings(const PlanPass& pp, int r, const int32_t* store_q)
+{
+    const int b = pp.hdr.b, tb = b - r;
+    auto check = [&](const StageHdr& m) {
+        uint32_t seen = 0;
+        for (int j = 0; j < r; j++) seen |= 1u << m.w[j];
+        for (int i = 0; i < tb; i++) {
+            if (m.tpos[i] < 0 || m.tpos[i] >= b || (seen & (1u << m.tpos[i])))
+                throw std::runtime_error("pass mapping repeats a local position");
+            seen |= 1u << m.tpos[i];
+        }
+        if (seen != ((1u << b) - 1)) throw std::runtime_error("pass mapping misses a local position");
+    };
+    check(pp.hdr.nat);
+    check(pp.hdr.out);
+    for (const StageHdr& st : pp.stages) check(st);
+    if (store_q) {
+        uint64_t a = 0, c = 0;
+        for (int j = 0; j < b; j++) {
+            a |= 1ull << pp.hdr.local_q[j];
+            c |= 1ull << store_q[j];
+        }
+        if (a != c || popc(c) != b) throw std::runtime_error("store map is not a permutation of the block's qubits");
+    }
+}
+
 std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in, const PlanOptions& opt, int elem)
 {
     if (n < 1 || n > kMaxQubits) throw std::runtime_error("qubit count out of range");
@@ -911,68 +999,78 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
 
     std::vector<char> done(items.size(), 0);
     std::vector<PlanPass> passes;
-    size_t first = 0;
-    while (true) {
-        while (first < items.size() && done[first]) first++;
-        if (first >= items.size()) break;
+    const int coal = (b == n) ? 0 : std::min(opt.coalesce, b);
+    const bool staged = opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9;
+    // Qubit moves: items keep their own (logical) qubit numbers; logical qubit
+    // q sits at state bit phys[q]. The block always holds state bits
+    // 0..coal-1 (contiguous runs); with `park`, a pass's store may permute its
+    // local qubits, so that the logical qubits the next pass needs sit on
+    // those bits and take no extra room in its block. The last pass sends
+    // every qubit back to its own bit (an extra pass with no gates if the last
+    // one cannot). A permutation of local qubits at the store only changes
+    // where each amplitude is written, so the result equals applying the
+    // gates in order.
+    const bool park = opt.park && staged && n_states == 1 && coal > 0 && b < n;
+    int phys[64], logi[64];
+    for (int q = 0; q < 64; q++) phys[q] = logi[q] = q;
+    auto to_phys = [&](uint64_t m) {
+        uint64_t r = 0;
+        for (int q = 0; q < n; q++)
+            if (m & (1ull << q)) r |= 1ull << phys[q];
+        return r;
+    };
 
-        uint64_t S0 = 0;
-        if (b == n) {
-            S0 = all;
-        } else {
-            for (int q = 0; q < std::min(opt.coalesce, b); q++) S0 |= 1ull << q;
-        }
-        // In-order scan from the first pending item: an item is taken when its
-        // dense qubits are (or, with `grow`, can still be made) local and no
-        // skipped earlier item it does not commute with blocks it. Returns
-        // the number taken; fills `taken` and the final local set when given.
-        auto scan = [&](uint64_t& S, bool grow, std::vector<size_t>* taken) {
-            uint64_t blk_dense = 0, blk_diag = 0;
-            int ops = 0, grads = 0, scanned = 0, count = 0;
-            for (size_t i = first; i < items.size() && scanned < opt.lookahead; i++) {
-                if (done[i]) continue;
-                scanned++;
-                const ItemBits& it = ib[i];
-                bool ok = !(it.dense & (blk_dense | blk_diag)) && !(it.diag & blk_dense);
-                if (ok) {
-                    const uint64_t need = it.dense & ~S;
-                    if ((need && (!grow || popc(S | need) > b)) || ops + it.n_ops > opt.max_ops ||
-                        (items[i].grad && grads >= kMaxGradPerPass))
-                        ok = false;
-                    else S |= need;
-                    if (ok && grow && opt.want_local) {
-                        const uint64_t w = it.want & ~S;
-                        if (w && popc(S | w) <= b - opt.want_reserve) S |= w;
-                    }
-                }
-                if (ok) {
-                    if (taken) taken->push_back(i);
-                    count++;
-                    ops += it.n_ops;
-                    grads += items[i].grad ? 1 : 0;
-                } else {
-                    blk_dense |= it.dense;
-                    blk_diag |= it.diag;
-                    if ((blk_dense & all) == all) break;  // nothing later can be taken
+    // In-order scan from the first pending item: an item is taken when its
+    // dense qubits are (or, with `grow`, can still be made) local and no
+    // skipped earlier item it does not commute with blocks it. Returns the
+    // number taken; fills `taken` and the final local set when given.
+    auto scan = [&](size_t first, uint64_t& S, bool grow, std::vector<size_t>* taken) {
+        uint64_t blk_dense = 0, blk_diag = 0;
+        int ops = 0, grads = 0, scanned = 0, count = 0;
+        for (size_t i = first; i < items.size() && scanned < opt.lookahead; i++) {
+            if (done[i]) continue;
+            scanned++;
+            const ItemBits& it = ib[i];
+            bool ok = !(it.dense & (blk_dense | blk_diag)) && !(it.diag & blk_dense);
+            if (ok) {
+                const uint64_t need = it.dense & ~S;
+                if ((need && (!grow || popc(S | need) > b)) || ops + it.n_ops > opt.max_ops ||
+                    (items[i].grad && grads >= kMaxGradPerPass))
+                    ok = false;
+                else S |= need;
+                if (ok && grow && opt.want_local) {
+                    const uint64_t w = it.want & ~S;
+                    if (w && popc(S | w) <= b - opt.want_reserve) S |= w;
                 }
             }
-            return count;
-        };
-        // Local set, first choice: grown in item order (each item's qubits join
-        // while there is room).
+            if (ok) {
+                if (taken) taken->push_back(i);
+                count++;
+                ops += it.n_ops;
+                grads += items[i].grad ? 1 : 0;
+            } else {
+                blk_dense |= it.dense;
+                blk_diag |= it.diag;
+                if ((blk_dense & all) == all) break;  // nothing later can be taken
+            }
+        }
+        return count;
+    };
+    // Local set of a pass that must hold S0 (logical qubits): first choice,
+    // grown in item order (each item's qubits join while there is room);
+    // second choice, from the first pending item's qubits, add one candidate
+    // item's missing qubits at a time, the ones that let the most further
+    // items in per added qubit. Keeps whichever set takes more items.
+    auto choose = [&](size_t first, uint64_t S0, std::vector<size_t>& taken) {
         uint64_t S = S0;
-        std::vector<size_t> taken;
-        scan(S, true, &taken);
-        // Second choice: start from the first pending item's qubits and add,
-        // one candidate item at a time, the missing qubits that let the most
-        // further items in per added qubit. The pass keeps whichever set
-        // takes more items.
+        taken.clear();
+        scan(first, S, true, &taken);
         if (opt.best_gain && b < n) {
             uint64_t S1 = S0 | ib[first].dense;
             if (popc(S1) <= b) {
                 while (true) {
                     uint64_t t = S1;
-                    const int base = scan(t, false, nullptr);
+                    const int base = scan(first, t, false, nullptr);
                     double best = 0;
                     uint64_t best_S = 0;
                     int seen = 0;
@@ -982,7 +1080,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                         const uint64_t need = ib[i].dense & ~S1;
                         if (!need || popc(S1 | need) > b) continue;
                         uint64_t u = S1 | need;
-                        const double gain = (double)(scan(u, false, nullptr) - base) / popc(need);
+                        const double gain = (double)(scan(first, u, false, nullptr) - base) / popc(need);
                         if (gain > best) {
                             best = gain;
                             best_S = S1 | need;
@@ -993,15 +1091,35 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                 }
                 std::vector<size_t> taken1;
                 uint64_t u = S1;
-                scan(u, false, &taken1);
+                scan(first, u, false, &taken1);
                 if (taken1.size() >= taken.size()) {
                     taken.swap(taken1);
                     S = S1;
                 }
             }
         }
+        return S;
+    };
+
+    size_t first = 0;
+    while (true) {
+        while (first < items.size() && done[first]) first++;
+        if (first >= items.size()) break;
+
+        uint64_t S0 = 0;
+        if (b == n) {
+            S0 = all;
+        } else {
+            for (int q = 0; q < coal; q++) S0 |= 1ull << logi[q];
+        }
+        std::vector<size_t> taken;
+        uint64_t S = choose(first, S0, taken);
         if (taken.empty()) throw std::runtime_error("planner made no progress");
-        for (int q = 0; q < n && popc(S) < b; q++) S |= 1ull << q;  // fill with the lowest qubits
+        // fill with qubits away from their own bit (so that they can go back),
+        // then with the lowest qubits
+        for (int q = 0; q < n && popc(S) < b; q++)
+            if (phys[q] != q) S |= 1ull << q;
+        for (int q = 0; q < n && popc(S) < b; q++) S |= 1ull << q;
         int grads = 0;
         for (size_t i : taken) {
             done[i] = 1;
@@ -1011,7 +1129,10 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         PlanPass pp;
         const bool single = taken.size() == 1 && !items[taken[0]].grad;
         if (single && opt.single_gate_sweeps && n_states == 1) {
-            const HostGate& g = items[taken[0]].g;
+            HostGate g = items[taken[0]].g;
+            for (int e = 0; e < 2; e++)
+                if (g.q[e] >= 0) g.q[e] = phys[g.q[e]];
+            g.ctrl = to_phys(g.ctrl);
             pp.kind = g.kind == G_DENSE1 ? PlanPass::SWEEP1 : g.kind == G_DENSE2 ? PlanPass::SWEEP2
                                                                                 : PlanPass::SWEEPDIAG;
             pp.gate = pp.kind == PlanPass::SWEEPDIAG ? sweep_form(g) : g;
@@ -1024,15 +1145,16 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         PassHdr& h = pp.hdr;
         h.b = b;
         h.n_outer = n - b;
-        int pos_of[64];
+        const uint64_t Sp = to_phys(S);
+        int pos_of[64];  // local position of each logical qubit of S
         for (int q = 0; q < 64; q++) pos_of[q] = -1;
         int j = 0, o = 0;
-        for (int q = 0; q < n; q++) {
-            if (S & (1ull << q)) {
-                pos_of[q] = j;
-                h.local_q[j++] = q;
+        for (int p = 0; p < n; p++) {
+            if (Sp & (1ull << p)) {
+                pos_of[logi[p]] = j;
+                h.local_q[j++] = p;
             } else {
-                h.outer_q[o++] = q;
+                h.outer_q[o++] = p;
             }
         }
         auto local_mask = [&](uint64_t m) {
@@ -1041,6 +1163,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                 if ((m & (1ull << q)) && pos_of[q] >= 0) r |= 1u << pos_of[q];
             return r;
         };
+        auto phys_of = [&](int q) { return q >= 0 ? phys[q] : -1; };
         for (size_t i : taken) {
             const PlanItem& it = items[i];
             const HostGate& g = it.g;
@@ -1048,7 +1171,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                 TileOp t{};
                 t.kind = T_GRAD;
                 t.a = pos_of[g.q[0]];
-                t.oa = g.q[0];
+                t.oa = phys_of(g.q[0]);
                 t.c = -1;
                 t.oc = -1;
                 t.slot = it.grad_slot;
@@ -1067,7 +1190,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             TileOp t{};
             t.kind = g.kind == G_DENSE1 ? T_DENSE1 : g.kind == G_DENSE2 ? T_DENSE2 : T_DIAG;
             t.lctrl = local_mask(g.ctrl);
-            t.gctrl = g.ctrl & ~S;
+            t.gctrl = to_phys(g.ctrl & ~S);
             t.mat = (int32_t)pp.mats.size();
             t.gen = GEN_NONE;
             t.slot = -1;
@@ -1085,23 +1208,202 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                 for (int e = 0; e < 16; e++) pp.mats.push_back(g.m[e]);
             } else {
                 t.a = g.q[0] >= 0 ? pos_of[g.q[0]] : -1;
-                t.oa = g.q[0];
+                t.oa = phys_of(g.q[0]);
                 t.c = g.q[1] >= 0 ? pos_of[g.q[1]] : -1;
-                t.oc = g.q[1];
+                t.oc = phys_of(g.q[1]);
                 for (int e = 0; e < 4; e++) pp.mats.push_back(g.m[e]);
             }
             pp.ops.push_back(t);
         }
         h.n_ops = (int32_t)pp.ops.size();
         h.n_grad = grads;
-        if (opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9) {
+
+        // Where the store writes each local position (park only).
+        int32_t store_q[kMaxLocal];
+        int store_first[8];
+        bool moved = false;
+        if (park) {
+            size_t nf = first;
+            while (nf < items.size() && done[nf]) nf++;
+            // new state bit of each logical qubit of S, starting from where it is
+            int np[64], nl[64];
+            for (int q = 0; q < n; q++) {
+                np[q] = phys[q];
+                nl[phys[q]] = q;
+            }
+            auto put = [&](int x, int slot) {  // logical x onto state bit `slot` (both in the block)
+                const int y = nl[slot], px = np[x];
+                np[x] = slot;
+                nl[slot] = x;
+                np[y] = px;
+                nl[px] = y;
+            };
+            int want[8], slot_of[8];
+            int nw = 0;
+            const bool last = nf >= items.size();
+            if (!last) {
+                // the logical qubits the next pass would hold with a free choice
+                std::vector<size_t> t2;
+                const uint64_t Sn = choose(nf, 0, t2) & S;
+                auto add_want = [&](int q) {
+                    for (int k = 0; k < nw; k++)
+                        if (want[k] == q) return;
+                    want[nw++] = q;
+                };
+                // those of the block first (the ones already on the run bits
+                // before the others), then the block's qubits in the order the
+                // pending items first use them
+                for (int k = 0; k < coal; k++)
+                    if (Sn & (1ull << nl[k])) add_want(nl[k]);
+                for (int q = 0; q < n && nw < coal; q++)
+                    if (Sn & (1ull << q)) add_want(q);
+                for (size_t i = nf; i < items.size() && nw < coal; i++) {
+                    if (done[i]) continue;
+                    const uint64_t d = ib[i].dense & S;
+                    for (int q = 0; q < n && nw < coal; q++)
+                        if (d & (1ull << q)) add_want(q);
+                }
+                // a wanted qubit already on a run bit stays there; the others
+                // take the run bits left
+                bool used_slot[8] = {false};
+                for (int k = 0; k < nw; k++) {
+                    slot_of[k] = np[want[k]] < coal ? np[want[k]] : -1;
+                    if (slot_of[k] >= 0) used_slot[slot_of[k]] = true;
+                }
+                for (int k = 0; k < nw; k++)
+                    if (slot_of[k] < 0)
+                        for (int sl = 0; sl < coal; sl++)
+                            if (!used_slot[sl]) {
+                                slot_of[k] = sl;
+                                used_slot[sl] = true;
+                                break;
+                            }
+            } else {
+                // last pass: the qubits of the run bits back to them
+                for (int k = 0; k < coal; k++)
+                    if (S & (1ull << k)) {
+                        want[nw] = k;
+                        slot_of[nw++] = k;
+                    }
+            }
+            for (int k = 0; k < nw; k++) put(want[k], slot_of[k]);
+            // the others back to their own bit where that bit is in the block and
+            // holds a qubit not on a run bit
+            for (int q = coal; q < n; q++) {
+                if (!(S & (1ull << q)) || np[q] == q || np[q] < coal) continue;
+                if (!(Sp & (1ull << q))) continue;
+                const int y = nl[q];
+                if (np[y] < coal) continue;
+                put(q, q);
+            }
+            for (int jj = 0; jj < b; jj++) {
+                const int x = logi[h.local_q[jj]];
+                store_q[jj] = np[x];
+                if (np[x] != h.local_q[jj]) moved = true;
+            }
+            if (moved) {
+                for (int k = 0; k < coal; k++) {
+                    store_first[k] = -1;
+                    for (int jj = 0; jj < b; jj++)
+                        if (store_q[jj] == k) store_first[k] = jj;
+                    if (store_first[k] < 0) throw std::runtime_error("store map lost a run bit");
+                }
+                for (int q = 0; q < n; q++) {
+                    phys[q] = np[q];
+                    logi[np[q]] = q;
+                }
+            }
+        }
+        if (staged) {
             if (opt.fuse_gates) fuse_ops(pp);
-            plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem, opt.lds_elem > 0 ? opt.lds_elem : elem);
+            uint32_t moved_mask = 0;
+            if (moved)
+                for (int jj = 0; jj < b; jj++)
+                    if (store_q[jj] != h.local_q[jj]) moved_mask |= 1u << jj;
+            plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem, opt.lds_elem > 0 ? opt.lds_elem : elem,
+                        moved ? store_first : nullptr, moved_mask);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
             set_reg_codes(pp, opt.reg_bits);
-            set_io_offsets(pp.hdr, opt.reg_bits);
+            set_io_offsets(pp.hdr, opt.reg_bits, moved ? store_q : nullptr);
+            check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);
         }
+        pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
+        passes.push_back(std::move(pp));
+    }
+    // Qubits still away from their own bit: passes with no gates that move
+    // them back, a few pairs (qubit, holder of its bit) at a time.
+    while (park) {
+        uint64_t away = 0;
+        for (int q = 0; q < n; q++)
+            if (phys[q] != q) away |= 1ull << q;
+        if (!away) break;
+        uint64_t S = 0;
+        for (int k = 0; k < coal; k++) S |= 1ull << logi[k];
+        // whole cycles of the permutation while they fit, else pairs
+        for (int q = 0; q < n; q++) {
+            if (!(away & (1ull << q)) || (S & (1ull << q))) continue;
+            uint64_t cyc = 0;
+            for (int x = q; !(cyc & (1ull << x)); x = logi[x]) cyc |= 1ull << x;
+            if (popc(S | cyc) <= b) S |= cyc;
+        }
+        for (int q = 0; q < n && popc(S) < b - 1; q++) {
+            if (!(away & (1ull << q)) || (S & (1ull << q))) continue;
+            S |= (1ull << q) | (1ull << logi[q]);
+        }
+        for (int q = 0; q < n && popc(S) < b; q++) S |= 1ull << q;
+        PlanPass pp;
+        pp.kind = PlanPass::BLOCK;
+        PassHdr& h = pp.hdr;
+        h.b = b;
+        h.n_outer = n - b;
+        const uint64_t Sp = to_phys(S);
+        int j = 0, o = 0;
+        for (int p = 0; p < n; p++) {
+            if (Sp & (1ull << p)) h.local_q[j++] = p;
+            else h.outer_q[o++] = p;
+        }
+        int np[64], nl[64];
+        for (int q = 0; q < n; q++) {
+            np[q] = phys[q];
+            nl[phys[q]] = q;
+        }
+        for (int q = 0; q < n; q++) {
+            if (!(S & (1ull << q)) || np[q] == q || !(Sp & (1ull << q))) continue;
+            const int y = nl[q], pq = np[q];
+            np[q] = q;
+            nl[q] = q;
+            np[y] = pq;
+            nl[pq] = y;
+        }
+        // the run bits must stay in the block's run positions
+        int32_t store_q[kMaxLocal];
+        int store_first[8];
+        for (int jj = 0; jj < b; jj++) store_q[jj] = np[logi[h.local_q[jj]]];
+        for (int k = 0; k < coal; k++) {
+            store_first[k] = -1;
+            for (int jj = 0; jj < b; jj++)
+                if (store_q[jj] == k) store_first[k] = jj;
+            if (store_first[k] < 0) throw std::runtime_error("restore map lost a run bit");
+        }
+        bool progress = false;
+        for (int q = 0; q < n; q++) {
+            progress |= np[q] == q && phys[q] != q;
+            phys[q] = np[q];
+            logi[np[q]] = q;
+        }
+        if (!progress) throw std::runtime_error("qubit restore made no progress");
+        h.n_ops = 0;
+        h.n_grad = 0;
+        uint32_t moved_mask = 0;
+        for (int jj = 0; jj < b; jj++)
+            if (store_q[jj] != h.local_q[jj]) moved_mask |= 1u << jj;
+        plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem, opt.lds_elem > 0 ? opt.lds_elem : elem, store_first,
+                    moved_mask);
+        pp.reg_bits = opt.reg_bits;
+        set_reg_codes(pp, opt.reg_bits);
+        set_io_offsets(pp.hdr, opt.reg_bits, store_q);
+        check_mappings(pp, opt.reg_bits, store_q);
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
         passes.push_back(std::move(pp));
     }

@@ -236,6 +236,8 @@ struct PlanOptions {
     int wave_mode = 2;            // 0: workgroup-wide exchanges only; 1: fixed wave positions,
                                   // within-wave exchanges while they hold; 2: wave positions picked
                                   // from the pass's least-used positions
+    bool park = false;            // move qubits between passes: each pass's store may permute its
+                                  // local qubits (single-state register passes only)
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its

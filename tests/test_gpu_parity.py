@@ -134,6 +134,32 @@ def test_random_circuit_22q_against_oracle(qv, dtype):
     assert maxabs(host(st), want) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("kind,n,seed", [("cx", 16, 0), ("cx", 18, 5), ("cz", 20, 2), ("qft", 18, 1),
+                                         ("mixed", 17, 9)])
+def test_qubit_moves_between_passes(qv, monkeypatch, kind, n, seed, dtype):
+    """Plans whose passes permute their local qubits at the store (and end
+    with every qubit back on its own bit, by an extra pass when needed) give
+    the oracle's state, as do plans that keep every qubit in place."""
+    print(f"qubit moves {kind} n={n} seed={seed} dtype={dtype}", flush=True)
+    if kind == "qft":
+        circ = C.qft(n)
+    elif kind == "mixed":
+        circ = C.random_mixed_circuit(n, 400, seed)
+    else:
+        circ = C.random_u3_layers(n, 20, seed, entangler=kind)
+    x = C.random_basis_index(n, seed)
+    want = oracle.run(circ, n, x0=x)
+    passes = {}
+    for park in ("1", "0"):
+        monkeypatch.setenv("QVEC_PARK", park)
+        passes[park] = qv.plan_stats(n, dtype, circ)["n_passes"]
+        st = qv.State(n, dtype).set_basis(x).apply(circ)
+        err = maxabs(host(st), want)
+        assert err <= TOL[dtype], (park, err)
+    assert passes["1"] <= passes["0"] + 1, passes
+
+
 # ------------------------------------------------------------ closed forms ---
 
 @pytest.mark.parametrize("dtype", DTYPES)
