@@ -4,6 +4,8 @@
 // Amplitudes are native 2-vectors (re, im): d2 (complex128, 16 B) or f2
 // (complex64, 8 B), so every amplitude moves with one 16-/8-byte access.
 // All indices are 64-bit (2^34 amplitudes at most).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace qv {
@@ -12,6 +14,29 @@ static unsigned grid_for(uint64_t items, uint64_t per_block)
 {
     const uint64_t g = (items + per_block - 1) / per_block;
     return (unsigned)(g ? g : 1);
+}
+
+// A dispatch holds fewer than 2^32 work-items, so large states give each
+// thread more items: the smallest of pref, 2, 4, 8, 16 that keeps the grid
+// at 2^31 work-items or fewer (2^34 amplitudes need 8).
+static int items_per_thread(uint64_t items, int pref)
+{
+    int p = pref;
+    while (p < 16 && (items + p - 1) / p > (1ull << 31)) p *= 2;
+    return p;
+}
+
+// Calls f(std::integral_constant<int, P>) for P = items_per_thread(items, pref).
+template <typename F>
+static void with_per_thread(uint64_t items, int pref, F&& f)
+{
+    switch (items_per_thread(items, pref)) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 16>{}); break;
+    }
 }
 
 // ----------------------------------------------------------- basis init ---
@@ -35,9 +60,13 @@ __global__ __launch_bounds__(kThreads) void k_init_basis(T* __restrict__ psi, ui
 template <typename T>
 hipError_t launch_init_basis(T* psi, int n, uint64_t x, hipStream_t st)
 {
-    constexpr int P = 8;
+    // one amplitude per thread (as for the copy) while the grid allows
     const uint64_t N = 1ull << n;
-    hipLaunchKernelGGL((k_init_basis<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi, N, x);
+    with_per_thread(N, 1, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_init_basis<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi, N,
+                           x);
+    });
     return hipGetLastError();
 }
 
@@ -119,26 +148,29 @@ __global__ __launch_bounds__(kThreads) void k_sweep1_lane(T* __restrict__ psi, u
 template <typename T>
 hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
 {
-    // Measured on MI355X at 29 qubits: 2 pairs per thread is fastest while
-    // the partner stride is small, 4 once it is large.
+    // Measured on MI355X at 29 qubits: one pair (or amplitude) per thread is
+    // fastest while the partner stride is below 2^20 amplitudes (more,
+    // smaller workgroups walk memory more evenly: 6.8 TB/s for the lane
+    // form, about 6.1 for strides of 2^13..2^19 against 5.7 with 2 or 4
+    // pairs), 4 pairs once it is larger (about 5.65 TB/s either way).
     const int k = g.q[0];
     const uint64_t mask = g.ctrl | (1ull << k);
     const Ins ins = make_ins(mask);
     const uint64_t npairs = 1ull << (n - ins.cnt);
     const T u00 = to_dev<T>(g.m[0]), u01 = to_dev<T>(g.m[1]), u10 = to_dev<T>(g.m[2]), u11 = to_dev<T>(g.m[3]);
     if (g.ctrl == 0 && k < 3 && n >= 8) {
-        constexpr int P = 4;
         const uint64_t N = 1ull << n;
-        hipLaunchKernelGGL((k_sweep1_lane<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi, N, k,
-                           u00, u01, u10, u11);
-    } else if (k < 16) {
-        constexpr int P = 2;
-        hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
-                           npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+        with_per_thread(N, 1, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL((k_sweep1_lane<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi,
+                               N, k, u00, u01, u10, u11);
+        });
     } else {
-        constexpr int P = 4;
-        hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
-                           npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+        with_per_thread(npairs, k < 20 ? 1 : 4, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
+                               npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+        });
     }
     return hipGetLastError();
 }
@@ -199,7 +231,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(T* __restrict__ psi, uint64
 template <typename T>
 hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
 {
-    constexpr int P = 2;
     const uint64_t mask = g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]);
     const Ins ins = make_ins(mask);
     const uint64_t nquads = 1ull << (n - ins.cnt);
@@ -208,8 +239,11 @@ hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
         m.v[2 * e] = g.m[e].real();
         m.v[2 * e + 1] = g.m[e].imag();
     }
-    hipLaunchKernelGGL((k_sweep2<T, P>), dim3(grid_for(nquads, kThreads * P)), dim3(kThreads), 0, st, psi,
-                       nquads, g.q[0], g.q[1], ins, g.ctrl, m);
+    with_per_thread(nquads, 2, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_sweep2<T, P>), dim3(grid_for(nquads, kThreads * P)), dim3(kThreads), 0, st, psi,
+                           nquads, g.q[0], g.q[1], ins, g.ctrl, m);
+    });
     return hipGetLastError();
 }
 
@@ -246,12 +280,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep_diag(T* __restrict__ psi, ui
 template <typename T>
 hipError_t launch_sweep_diag(T* psi, int n, const HostGate& g, hipStream_t st)
 {
-    constexpr int P = 4;
     const Ins ins = make_ins(g.ctrl);
     const uint64_t count = 1ull << (n - ins.cnt);
-    hipLaunchKernelGGL((k_sweep_diag<T, P>), dim3(grid_for(count, kThreads * P)), dim3(kThreads), 0, st, psi,
-                       count, ins, g.ctrl, g.q[0], g.q[1], to_dev<T>(g.m[0]), to_dev<T>(g.m[1]),
-                       to_dev<T>(g.m[2]), to_dev<T>(g.m[3]));
+    with_per_thread(count, 4, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_sweep_diag<T, P>), dim3(grid_for(count, kThreads * P)), dim3(kThreads), 0, st, psi,
+                           count, ins, g.ctrl, g.q[0], g.q[1], to_dev<T>(g.m[0]), to_dev<T>(g.m[1]),
+                           to_dev<T>(g.m[2]), to_dev<T>(g.m[3]));
+    });
     return hipGetLastError();
 }
 
@@ -595,9 +631,11 @@ __global__ __launch_bounds__(kThreads) void k_pauli_apply(const T* __restrict__ 
 template <typename T>
 hipError_t launch_pauli_apply(const T* psi, T* dst, int n, const TermBatch& tb, bool accumulate, hipStream_t st)
 {
-    constexpr int P = 4;
-    hipLaunchKernelGGL((k_pauli_apply<T, P>), dim3(grid_for(1ull << n, kThreads * P)), dim3(kThreads), 0, st, psi,
-                       dst, n, tb, accumulate ? 1 : 0);
+    with_per_thread(1ull << n, 4, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_pauli_apply<T, P>), dim3(grid_for(1ull << n, kThreads * P)), dim3(kThreads), 0, st,
+                           psi, dst, n, tb, accumulate ? 1 : 0);
+    });
     return hipGetLastError();
 }
 
@@ -749,10 +787,13 @@ __global__ __launch_bounds__(kThreads) void k_copy(d2* __restrict__ dst, const d
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 {
-    constexpr int P = 4;  // fastest of 4/8/16 on MI355X
+    // one element per thread while the grid allows: 6.6 TB/s on MI355X, against 5.8 with 4
     const uint64_t n16 = bytes / 16;
-    hipLaunchKernelGGL((k_copy<P>), dim3(grid_for(n16, kThreads * P)), dim3(kThreads), 0, st,
-                       reinterpret_cast<d2*>(dst), reinterpret_cast<const d2*>(src), n16);
+    with_per_thread(n16, 1, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_copy<P>), dim3(grid_for(n16, kThreads * P)), dim3(kThreads), 0, st,
+                           reinterpret_cast<d2*>(dst), reinterpret_cast<const d2*>(src), n16);
+    });
     return hipGetLastError();
 }
 
