@@ -146,3 +146,33 @@ def test_24q_instance_of_33q_generator_against_oracle(qv):
         torch.cuda.synchronize()
         got = st.tensor.to(torch.complex128).cpu().numpy()
         assert np.max(np.abs(got - want)) <= tol, dtype
+
+
+def test_34q_c64_streaming_launches(qv):
+    """34 qubits complex64 (128 GiB, 2^34 amplitudes: more than one dispatch
+    can hold one per work-item): basis init, unfused X sweeps on low, middle
+    and high targets (the lane, one-pair and four-pair forms), and fused
+    Hadamards on every qubit."""
+    n = 34
+    if mem_gib() < 160:
+        pytest.skip("needs 128 GiB of device memory")
+    print("34q c64", flush=True)
+    x = C.random_basis_index(n, 3)
+    st = qv.State(n, torch.complex64).set_basis(x)
+    targets = [0, 2, 15, 25, 33]
+    st.apply([C.gate("x", q) for q in targets], fused=False)
+    y = x
+    for q in targets:
+        y ^= 1 << q
+    idx = torch.from_numpy(np.unique(np.concatenate([[0, y, (1 << n) - 1],
+                                                     C.rng_for(5).integers(0, 1 << n, size=4096)])))
+    got = st.tensor[idx.cuda()].cpu().numpy()
+    want = np.where(idx.numpy() == y, 1.0, 0.0)
+    assert np.max(np.abs(got - want)) == 0.0
+    assert abs(st.norm2() - 1) <= 1e-6
+    st.set_basis(0).apply([C.gate("h", q) for q in range(n)])
+    got = st.tensor[idx.cuda()].cpu().numpy()
+    assert np.max(np.abs(got - 2.0 ** (-n / 2))) <= 1e-5 * 2.0 ** (-n / 2) * 10
+    assert abs(st.norm2() - 1) <= 1e-5
+    del st
+    torch.cuda.empty_cache()
