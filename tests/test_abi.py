@@ -134,12 +134,16 @@ def test_plan_fuses_bench_circuits():
     assert rc == B.SV_OK and st.n_passes < 40
 
 
+@pytest.mark.parametrize("park", ["0", "1"])
 @pytest.mark.parametrize("dtype", [B.SV_C128, B.SV_C64])
-def test_planner_handles_benchmark_and_random_circuits(dtype):
+def test_planner_handles_benchmark_and_random_circuits(dtype, park, monkeypatch):
     """The planner raises on an internal inconsistency (an op outside its
     stage's window, a phase term on an unmapped position, no progress).
     Plans for the benchmark circuits, their inverses, the 33-qubit circuit,
-    the ansatz and random circuits over every op must all succeed."""
+    the ansatz and random circuits over every op must all succeed, also when
+    passes move qubits between state bits (it then also checks that every
+    store writes a permutation of its block's qubits)."""
+    monkeypatch.setenv("QVEC_PARK", park)
     def inverse(circ):
         out = []
         for g in reversed(circ):
