@@ -337,7 +337,7 @@ sv_status upload_tables(sv_state s, const std::vector<PlanPass>& passes, TableOf
         for (const TileOp& op : p.ops) {
             TileOp t = op;
             t.mat += (int32_t)im;
-            if (t.kind == T_PHASE) t.aux += (int32_t)ip;
+            if (t.kind == T_PHASE || t.kind == T_GRADZ) t.aux += (int32_t)ip;
             O[io++] = t;
         }
         for (const PhaseTerm& pt : p.phase) P[ip++] = pt;
@@ -449,6 +449,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.prefuse = o.fuse_gates && o.reg_bits > 0;
     // "1": passes may move qubits between state bits (fewer passes, but on
     // MI355X the extra store exchanges cost more than the passes saved)
+    const char* gr = std::getenv("QVEC_GROUP_READS");  // "0": every Z read of the adjoint sweep on its own
+    o.group_reads = !(gr && std::strcmp(gr, "0") == 0);
     const char* pk = std::getenv("QVEC_PARK");
     o.park = o.reg_bits > 0 && pk && std::strcmp(pk, "1") == 0;
     const char* wm = std::getenv("QVEC_WAVE_MODE");  // "0" | "1" | "2": see PlanOptions::wave_mode
@@ -860,11 +862,20 @@ sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const s
     std::vector<int> row_gate;  // result row -> gate index
     for (size_t p = 0; p < passes.size(); p++) {
         int local = 0;
-        for (TileOp& op : passes[p].ops)
+        for (TileOp& op : passes[p].ops) {
             if (op.kind == T_GRAD) {
                 row_gate.push_back(slot_gate[op.slot]);
                 op.slot = local++;
+            } else if (op.kind == T_GRADZ) {
+                for (int e = 0; e < op.cnt; e++) {
+                    ReadZ z;
+                    std::memcpy(&z, &passes[p].phase[op.aux + e], sizeof(z));
+                    row_gate.push_back(slot_gate[z.slot]);
+                    z.slot = local++;
+                    std::memcpy(&passes[p].phase[op.aux + e], &z, sizeof(z));
+                }
             }
+        }
         rows_per_pass[p] = local;
     }
     const int n_grad = (int)row_gate.size();

@@ -614,6 +614,41 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 }
                 break;
             }
+            case RC_GZM: {
+                // several Z reads: p_k = Im(conj(lambda_k) phi_k) once, then a
+                // read of window bit j is sum_k (-1)^(k_j) p_k and a read of a
+                // thread bit or an outer qubit is +-sum_k p_k
+                if constexpr (NS == 2) {
+                    double S = 0, D[RB];
+#pragma unroll
+                    for (int j = 0; j < RB; j++) D[j] = 0;
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        const T f = v[0][k], m = v[1][k];
+                        const double p = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+                        S += p;
+#pragma unroll
+                        for (int j = 0; j < RB; j++) D[j] += ((k >> j) & 1) ? -p : p;
+                    }
+                    const ReadZ* rz = reinterpret_cast<const ReadZ*>(phase + op.aux);
+                    const uint32_t utid = (uint32_t)tid;
+                    for (int e = 0; e < op.cnt; e++) {
+                        const int zj = rz[e].j, ztb = rz[e].tbit, zoa = rz[e].oa, zslot = rz[e].slot;
+                        double val;
+                        if (zj >= 0) {
+                            val = D[0];
+#pragma unroll
+                            for (int j = 1; j < RB; j++) val = zj == j ? D[j] : val;
+                        } else {
+                            const bool bit = ztb >= 0 ? ((utid >> ztb) & 1u) != 0 : ((base >> zoa) & 1ull) != 0;
+                            val = bit ? -S : S;
+                        }
+                        val = wave_total(val);
+                        if (lane == 0) red[zslot * 8 + wave] = val;
+                    }
+                }
+                break;
+            }
 #define F_G(J)                                                   \
     if constexpr (NS == 2) {                                     \
         double acc = reg_grad_xy<T, RB, J>(v, (double)mats[cur.mat].x, (double)mats[cur.mat].y); \

@@ -412,6 +412,7 @@ int32_t reg_code(const TileOp& t)
     case T_DIAG: return RC_DIAG;
     case T_PHASE: return RC_PHASE;
     case T_GRAD: return t.gen == GEN_Z ? RC_GZ : RC_GXY + t.j0;
+    case T_GRADZ: return RC_GZM;
     default: return RC_NONE;
     }
 }
@@ -937,6 +938,83 @@ void merge_diagonals(PlanPass& pp, int r)
     pp.hdr.n_ops = (int32_t)pp.ops.size();
 }
 
+// Z reads of the adjoint sweep (Im <lambda|Z_q|phi>) commute with every op
+// that does not act densely on q (diagonal gates, other reads, gates on other
+// qubits), so each read may wait until such an op or the end of the pass.
+// Reads that wait together become one op that passes over the registers once:
+// with p_k = Im(conj(lambda_k) phi_k), a read of window bit j is
+// sum_k (-1)^(k_j) p_k, and a read of a thread bit or of a qubit outside the
+// block is +-sum_k p_k (the same sums, in the same order, as one read alone).
+void group_z_reads(PlanPass& pp, int r)
+{
+    const size_t n_st = pp.stages.size();
+    const int tb = pp.hdr.b - r;
+    std::vector<std::vector<TileOp>> out(n_st);
+    std::vector<TileOp> pending;
+    auto emit = [&](size_t si, const std::vector<TileOp>& reads) {
+        if (reads.empty()) return;
+        if (reads.size() == 1) {
+            out[si].push_back(reads[0]);
+            return;
+        }
+        const StageHdr& st = pp.stages[si];
+        TileOp t{};
+        t.kind = T_GRADZ;
+        t.a = t.c = t.oa = t.oc = -1;
+        t.j0 = t.j1 = -1;
+        t.gen = GEN_Z;
+        t.slot = -1;
+        t.aux = (int32_t)pp.phase.size();
+        t.cnt = (int32_t)reads.size();
+        for (const TileOp& g : reads) {
+            ReadZ z{};
+            z.j = z.tbit = z.oa = -1;
+            z.slot = g.slot;
+            if (g.a >= 0) {
+                z.j = window_index(st, r, g.a);
+                if (z.j < 0)
+                    for (int i = 0; i < tb; i++)
+                        if (st.tpos[i] == g.a) z.tbit = i;
+                if (z.j < 0 && z.tbit < 0) throw std::runtime_error("Z read on an unmapped position");
+            } else {
+                z.oa = g.oa;
+            }
+            PhaseTerm rec;
+            std::memcpy(&rec, &z, sizeof(rec));
+            pp.phase.push_back(rec);
+        }
+        out[si].push_back(t);
+    };
+    for (size_t si = 0; si < n_st; si++) {
+        const StageHdr& st = pp.stages[si];
+        for (int o = 0; o < st.n_ops; o++) {
+            const TileOp& t = pp.ops[st.op_begin + o];
+            if (t.kind == T_GRAD && t.gen == GEN_Z) {
+                pending.push_back(t);
+                continue;
+            }
+            if (t.kind != T_GRAD) {
+                // the reads on a qubit this op changes go first
+                const uint32_t dp = dense_positions(t);
+                std::vector<TileOp> now, keep;
+                for (const TileOp& g : pending) (g.a >= 0 && (dp >> g.a) & 1u ? now : keep).push_back(g);
+                emit(si, now);
+                pending.swap(keep);
+            }
+            out[si].push_back(t);
+        }
+    }
+    if (n_st) emit(n_st - 1, pending);
+    std::vector<TileOp> ops;
+    for (size_t si = 0; si < n_st; si++) {
+        pp.stages[si].op_begin = (int32_t)ops.size();
+        pp.stages[si].n_ops = (int32_t)out[si].size();
+        ops.insert(ops.end(), out[si].begin(), out[si].end());
+    }
+    pp.ops.swap(ops);
+    pp.hdr.n_ops = (int32_t)pp.ops.size();
+}
+
 }  // namespace
 
 // Every mapping of a staged pass places each local position exactly once,
@@ -1324,6 +1402,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                         moved ? store_first : nullptr, moved_mask);
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
+            if (opt.group_reads && grads > 1) group_z_reads(pp, opt.reg_bits);
             set_reg_codes(pp, opt.reg_bits);
             set_io_offsets(pp.hdr, opt.reg_bits, moved ? store_q : nullptr);
             check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);

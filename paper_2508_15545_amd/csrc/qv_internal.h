@@ -61,6 +61,8 @@ enum TileKind : int32_t {
     T_SWAP = 5,    // exchange of local qubits a and c
     T_PHASE = 6,   // product of diagonal gates as one phase per amplitude:
                    // terms phase[mat .. mat + cnt) (register kernel only)
+    T_GRADZ = 7,   // several Z reads in one pass over the registers: ReadZ
+                   // records phase[aux .. aux + cnt) (register kernel only)
 };
 
 struct TileOp {
@@ -101,6 +103,7 @@ enum RegCode : int32_t {
     RC_DIAG = 192,  // diagonal on any bits
     RC_PHASE = 193, // phase polynomial
     RC_GZ = 194,    // gradient read, G = Z
+    RC_GZM = 195,   // several gradient reads with G = Z (T_GRADZ)
     RC_GXY = 200,   // + j0: gradient read, G = X or Y on window bit j0
 };
 
@@ -135,6 +138,16 @@ struct PhaseHead {
     int32_t count[8];  // [0]: A, [1 + j]: window bit j
 };
 static_assert(sizeof(PhaseHead) == sizeof(PhaseTerm), "phase records share one array");
+// One read of a T_GRADZ op: Im <lambda|Z_q|phi> into partial row `slot`, with
+// q's bit at window bit j, else at thread bit tbit, else global qubit oa.
+struct ReadZ {
+    int32_t j;
+    int32_t tbit;
+    int32_t oa;
+    int32_t slot;
+    uint64_t pad[2];
+};
+static_assert(sizeof(ReadZ) == sizeof(PhaseTerm), "read records share the phase array");
 
 // A stage of a register-resident block pass: the amplitudes whose local
 // positions are w[0..r) are held by one thread (register bit j <-> position
@@ -238,6 +251,7 @@ struct PlanOptions {
                                   // from the pass's least-used positions
     bool park = false;            // move qubits between passes: each pass's store may permute its
                                   // local qubits (single-state register passes only)
+    bool group_reads = true;      // Z reads waiting together share one op (register kernel)
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its
