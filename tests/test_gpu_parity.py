@@ -265,6 +265,30 @@ def test_adjoint_matches_oracle(qv, n, layers, dtype):
     assert maxabs(back, e0) <= (1e-12 if dtype == torch.complex128 else 1e-5)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_adjoint_grouped_z_reads_match_single_reads(qv, monkeypatch, dtype):
+    """Z reads sharing one register pass (window, thread and outer-qubit
+    reads, 20 qubits, several blocks) give the gradients of reads taken one
+    by one, and both match the oracle. A read that waits is taken after ops
+    on other qubits, so the two agree to the rounding of those ops (complex64:
+    FP32 state updates)."""
+    n, layers = 20, 3
+    th = C.hea_params(n, layers, seed=11)
+    circ = C.hea(n, layers, th)
+    H = C.zz_x_chain(n)
+    P = 2 * n * layers
+    f_o, g_o = oracle.adjoint_grad(circ, n, H, P)
+    grads = {}
+    for group in ("1", "0"):
+        monkeypatch.setenv("QVEC_GROUP_READS", group)
+        st = qv.State(n, dtype).set_basis(0).apply(circ)
+        f, g = st.adjoint_grad(circ, H, P)
+        tol = 1e-10 if dtype == torch.complex128 else 1e-4
+        assert abs(f - f_o) <= tol and np.max(np.abs(g - g_o)) <= tol, group
+        grads[group] = g
+    assert np.max(np.abs(grads["1"] - grads["0"])) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
 def test_adjoint_rx_and_shared_parameters(qv):
     n = 6
     circ = [C.gate("h", q) for q in range(n)]
