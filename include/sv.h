@@ -123,6 +123,17 @@ typedef struct sv_plan_stats {
     int64_t n_phase_ops;    /* merged diagonal runs */
 } sv_plan_stats;
 
+/* Summary of one sv_host_apply call. */
+typedef struct sv_host_stats {
+    int64_t n_passes;      /* passes over the host state */
+    int64_t n_chunks;      /* chunks per pass: 2^(n - c) */
+    int64_t chunk_qubits;  /* c: qubits of a chunk (min(chunk_qubits, n)) */
+    int64_t high_qubits;   /* h: qubits of a chunk chosen per pass above its contiguous runs */
+    double bytes_h2d;      /* bytes copied host -> device */
+    double bytes_d2h;      /* bytes copied device -> host */
+    double seconds;        /* wall time of the call */
+} sv_host_stats;
+
 typedef struct sv_state_t* sv_state;
 
 /* Create a handle for an n-qubit state (Sec. II Eq. 1-2: 2^n amplitudes of
@@ -173,6 +184,26 @@ sv_status sv_apply_fused(sv_state s, const sv_gate* gates, int n_gates);
  * of this dtype (host only; nothing is launched). */
 sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gates,
                   sv_plan_stats* out);
+
+/* Out-of-core tier (Sec. III.B-C: the state lives in a slower tier and is
+ * staged block by block; every queued gate whose pairs lie in a staged block
+ * is applied before it is written back). The state is host_state, 2^n
+ * amplitudes of S_state bytes in pinned host memory (hipHostMalloc, or a
+ * torch tensor with pin_memory), 16-byte aligned, read and written in place.
+ * A chunk is the 2^c indices (c = min(chunk_qubits, n)) that agree outside
+ * the lowest c - h qubits (contiguous runs) and h high qubits chosen per
+ * pass; gates are taken in order while every qubit of each (targets and
+ * controls) lies in the chunk, and each chunk of a pass goes host -> device,
+ * through the fused device path (as sv_apply_fused on a c-qubit state) and
+ * back. Two device buffers of 2^c * S_state bytes are allocated for the call
+ * and freed before it returns; copies in, passes and copies out of three
+ * chunks overlap on three streams of the current device. Synchronous: the
+ * host state holds the result on return. stats may be NULL.
+ * Errors: SV_EINVAL (null or misaligned state, n or chunk_qubits out of
+ * range, a bad gate), SV_EUNSUPPORTED (a gate needs more high qubits than a
+ * chunk holds), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv_gate* gates,
+                        int n_gates, int chunk_qubits, sv_host_stats* stats);
 
 /* out = <psi|psi>, accumulated in double. Waits for the stream. */
 sv_status sv_norm2(sv_state s, double* out);

@@ -159,6 +159,23 @@ def copy(state: State, dst: torch.Tensor, src: torch.Tensor) -> None:
     check(lib().sv_copy(state.handle, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes))
 
 
+def host_apply(state: torch.Tensor, circuit, chunk_qubits: int) -> dict:
+    """Apply a circuit to a state held in pinned host memory (a 1-D complex
+    CPU tensor made with pin_memory=True, 2^n entries), chunk by chunk through
+    the GPU (sv_host_apply). Returns the call's statistics."""
+    if state.device.type != "cpu" or not state.is_pinned():
+        raise ValueError("the host state must be a pinned CPU tensor")
+    if state.dtype not in _DTYPES or not state.is_contiguous():
+        raise ValueError("the host state must be a contiguous complex64/complex128 tensor")
+    n = state.numel().bit_length() - 1
+    if state.numel() != 1 << n:
+        raise ValueError("the host state must have 2^n entries")
+    st = B.SvHostStats()
+    check(lib().sv_host_apply(ctypes.c_void_p(state.data_ptr()), n, _DTYPES[state.dtype], gate_array(circuit),
+                              len(circuit), chunk_qubits, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in B.SvHostStats._fields_}
+
+
 def plan_stats(n: int, dtype: torch.dtype, circuit) -> dict:
     st = B.SvPlanStats()
     check(lib().sv_plan(n, _DTYPES[dtype], gate_array(circuit), len(circuit), ctypes.byref(st)))

@@ -54,6 +54,18 @@ class SvPlanStats(ctypes.Structure):
     ]
 
 
+class SvHostStats(ctypes.Structure):
+    _fields_ = [
+        ("n_passes", ctypes.c_int64),
+        ("n_chunks", ctypes.c_int64),
+        ("chunk_qubits", ctypes.c_int64),
+        ("high_qubits", ctypes.c_int64),
+        ("bytes_h2d", ctypes.c_double),
+        ("bytes_d2h", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
 class SvError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"sv status {status}: {msg}")
@@ -75,6 +87,7 @@ SIGNATURES = {
     "sv_apply_unfused": (_st, [_vp, ctypes.POINTER(SvGate), _i]),
     "sv_apply_fused": (_st, [_vp, ctypes.POINTER(SvGate), _i]),
     "sv_plan": (_st, [_i, _i, ctypes.POINTER(SvGate), _i, ctypes.POINTER(SvPlanStats)]),
+    "sv_host_apply": (_st, [_vp, _i, _i, ctypes.POINTER(SvGate), _i, _i, ctypes.POINTER(SvHostStats)]),
     "sv_norm2": (_st, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "sv_expect": (_st, [_vp, ctypes.POINTER(SvPauli), _i, ctypes.POINTER(ctypes.c_double)]),
     "sv_apply_pauli_sum": (_st, [_vp, ctypes.POINTER(SvPauli), _i, _vp, ctypes.c_size_t]),

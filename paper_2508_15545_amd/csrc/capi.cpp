@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <new>
@@ -535,6 +536,74 @@ sv_status pauli_apply_impl(sv_state s, const T* psi, T* dst, const std::vector<T
 
 // ================================================================= C ABI ===
 
+// ------------------------------------------------------------ host tier ---
+// The state stays in pinned host memory and moves through the GPU in chunks
+// (QVecOpt Sec. III.B-C: a slower tier holds the state in blocks, a window of
+// blocks is staged, every queued gate whose pairs lie inside is applied, the
+// blocks are written back). A chunk is the set of 2^c indices that agree
+// outside c local qubits: the lowest m = c - h qubits (contiguous runs of 2^m
+// amplitudes) and h high qubits chosen per pass, so one chunk is 2^h runs.
+// Gates are taken in order while all their qubits (targets and controls) fit
+// in the pass's local set; each chunk is then a c-qubit state for the device
+// planner. Two device buffers and three streams overlap the copy-in of one
+// chunk, the passes over another and the copy-out of a third.
+namespace {
+
+struct HostPass {
+    std::vector<int> high;          // high local qubits (ascending), h of them
+    std::vector<sv_gate> gates;     // gates with qubits renumbered to chunk positions
+};
+
+int host_high_qubits(int n, int c) { return std::min(std::min(8, c / 2), n - c); }
+
+sv_status plan_host_passes(int n, int c, const sv_gate* gates, int n_gates, std::vector<HostPass>* out)
+{
+    const int h = host_high_qubits(n, c), m = c - h;
+    out->clear();
+    HostPass cur;
+    uint64_t high = 0;
+    auto close = [&]() {
+        // fill the high set to h qubits (lowest first) so that every chunk has 2^c amplitudes
+        for (int q = m; q < n && __builtin_popcountll(high) < h; q++) high |= 1ull << q;
+        cur.high.clear();
+        for (int q = m; q < n; q++)
+            if (high >> q & 1) cur.high.push_back(q);
+        int pos[64];
+        for (int q = 0; q < 64; q++) pos[q] = q < m ? q : -1;
+        for (int i = 0; i < h; i++) pos[cur.high[i]] = m + i;
+        for (sv_gate& g : cur.gates) {
+            const bool two = g.op == SV_OP_MATRIX2 || g.op == SV_OP_CNOT || g.op == SV_OP_CZ || g.op == SV_OP_CP ||
+                             g.op == SV_OP_SWAP;
+            g.qubits[0] = pos[g.qubits[0]];
+            if (two) g.qubits[1] = pos[g.qubits[1]];
+            for (int k = 0; k < g.n_controls; k++) g.controls[k] = pos[g.controls[k]];
+        }
+        out->push_back(cur);
+        cur = HostPass{};
+        high = 0;
+    };
+    for (int i = 0; i < n_gates; i++) {
+        const sv_gate& g = gates[i];
+        const bool two = g.op == SV_OP_MATRIX2 || g.op == SV_OP_CNOT || g.op == SV_OP_CZ || g.op == SV_OP_CP ||
+                         g.op == SV_OP_SWAP;
+        uint64_t need = 1ull << g.qubits[0];
+        if (two) need |= 1ull << g.qubits[1];
+        for (int k = 0; k < g.n_controls; k++) need |= 1ull << g.controls[k];
+        const uint64_t low = m >= 64 ? ~0ull : ((1ull << m) - 1);
+        const uint64_t add = need & ~low & ~high;
+        if (__builtin_popcountll(high | add) > h) {
+            if (cur.gates.empty()) return fail(SV_EUNSUPPORTED, "gate " + std::to_string(i) + " needs more high qubits than a chunk holds");
+            close();
+        }
+        high |= need & ~low;
+        cur.gates.push_back(g);
+    }
+    if (!cur.gates.empty()) close();
+    return SV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sv_last_error(void) { return g_err.c_str(); }
@@ -723,6 +792,136 @@ sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gate
         return fail(SV_EINVAL, std::string("planner: ") + e.what());
     }
     return SV_OK;
+}
+
+sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gates,
+                        int chunk_qubits, sv_host_stats* stats)
+{
+    g_err.clear();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (!host_state) return fail(SV_EINVAL, "null host state");
+    if (reinterpret_cast<uintptr_t>(host_state) % 16) return fail(SV_EINVAL, "host state not 16-byte aligned");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) return fail(SV_EINVAL, "n_qubits must be in [1, 34]");
+    if (chunk_qubits < 1 || chunk_qubits > kMaxQubits) return fail(SV_EINVAL, "chunk_qubits must be in [1, 34]");
+    const size_t elem = dtype == SV_C128 ? 16 : 8;
+    sv_state_t tmp;
+    tmp.n = n_qubits;
+    tmp.dtype = dtype;
+    tmp.elem = elem;
+    std::vector<HostGate> hg;
+    sv_status st = build_gates(&tmp, gates, n_gates, &hg);
+    if (st != SV_OK) return st;
+    const int n = n_qubits, c = std::min(chunk_qubits, n_qubits);
+    std::vector<HostPass> hp;
+    st = plan_host_passes(n, c, gates, n_gates, &hp);
+    if (st != SV_OK) return st;
+    const int h = host_high_qubits(n, c), m = c - h;
+    const uint64_t n_chunks = 1ull << (n - c), n_runs = 1ull << h;
+    const size_t run_bytes = ((size_t)1 << m) * elem, chunk_bytes = ((size_t)1 << c) * elem;
+    if (stats) {
+        stats->n_passes = (int64_t)hp.size();
+        stats->n_chunks = (int64_t)n_chunks;
+        stats->chunk_qubits = c;
+        stats->high_qubits = h;
+    }
+    if (hp.empty()) return SV_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+
+    hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    void* dbuf[2] = {nullptr, nullptr};
+    sv_state hs[2] = {nullptr, nullptr};
+    hipEvent_t ev[7] = {};  // in_done[2], comp_done[2], out_done[2], pass_done
+    hipEvent_t *in_done = ev, *comp_done = ev + 2, *out_done = ev + 4, &pass_done = ev[6];
+    auto body = [&]() -> sv_status {
+        HIP_TRY(hipStreamCreate(&s_in));
+        HIP_TRY(hipStreamCreate(&s_comp));
+        HIP_TRY(hipStreamCreate(&s_out));
+        for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (int b = 0; b < 2; b++) {
+            if (hipMalloc(&dbuf[b], chunk_bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                dbuf[b] = nullptr;
+                return fail(SV_ENOMEM, "device allocation of a chunk buffer failed");
+            }
+            sv_status a = sv_alloc(&hs[b], c, dtype, dbuf[b], chunk_bytes, s_comp);
+            if (a != SV_OK) return a;
+        }
+        bool used[2] = {false, false}, have_pass = false;
+        for (const HostPass& p : hp) {
+            std::vector<HostGate> cg;
+            sv_status bs = build_gates(hs[0], p.gates.data(), (int)p.gates.size(), &cg);
+            if (bs != SV_OK) return bs;
+            std::vector<PlanPass> plan;
+            try {
+                plan = plan_circuit(c, forward_items(cg), plan_options(c, elem, 1), (int)elem);
+            } catch (const std::exception& e) {
+                return fail(SV_EINVAL, std::string("planner: ") + e.what());
+            }
+            uint64_t local = (m >= 64) ? ~0ull : ((1ull << m) - 1);
+            for (int q : p.high) local |= 1ull << q;
+            int outer[64], n_outer = 0;
+            for (int q = 0; q < n; q++)
+                if (!(local >> q & 1)) outer[n_outer++] = q;
+            for (uint64_t k = 0; k < n_chunks; k++) {
+                const int b = (int)(k & 1);
+                uint64_t base = 0;
+                for (int i = 0; i < n_outer; i++) base |= ((k >> i) & 1ull) << outer[i];
+                if (used[b]) HIP_TRY(hipStreamWaitEvent(s_in, out_done[b], 0));
+                if (have_pass) HIP_TRY(hipStreamWaitEvent(s_in, pass_done, 0));
+                for (uint64_t r = 0; r < n_runs; r++) {
+                    uint64_t off = base;
+                    for (int i = 0; i < h; i++) off |= ((r >> i) & 1ull) << p.high[i];
+                    HIP_TRY(hipMemcpyAsync(static_cast<char*>(dbuf[b]) + r * run_bytes,
+                                           static_cast<const char*>(host_state) + off * elem, run_bytes,
+                                           hipMemcpyHostToDevice, s_in));
+                }
+                HIP_TRY(hipEventRecord(in_done[b], s_in));
+                HIP_TRY(hipStreamWaitEvent(s_comp, in_done[b], 0));
+                sv_status rs = dispatch(hs[b], [&](auto* psi) -> sv_status {
+                    using T = std::remove_pointer_t<decltype(psi)>;
+                    return run_plan<T>(hs[b], plan, psi, nullptr, 1, nullptr, nullptr);
+                });
+                if (rs != SV_OK) return rs;
+                HIP_TRY(hipEventRecord(comp_done[b], s_comp));
+                HIP_TRY(hipStreamWaitEvent(s_out, comp_done[b], 0));
+                for (uint64_t r = 0; r < n_runs; r++) {
+                    uint64_t off = base;
+                    for (int i = 0; i < h; i++) off |= ((r >> i) & 1ull) << p.high[i];
+                    HIP_TRY(hipMemcpyAsync(static_cast<char*>(host_state) + off * elem,
+                                           static_cast<const char*>(dbuf[b]) + r * run_bytes, run_bytes,
+                                           hipMemcpyDeviceToHost, s_out));
+                }
+                HIP_TRY(hipEventRecord(out_done[b], s_out));
+                used[b] = true;
+            }
+            // the next pass reads what this one writes back
+            HIP_TRY(hipEventRecord(pass_done, s_out));
+            have_pass = true;
+        }
+        HIP_TRY(hipStreamSynchronize(s_out));
+        return SV_OK;
+    };
+    sv_status res = body();
+    const std::string err = g_err;  // sv_free below clears the message
+    // release in dependency order; a failure above still drains the streams
+    for (hipStream_t q : {s_in, s_comp, s_out})
+        if (q && hipStreamSynchronize(q) != hipSuccess && res == SV_OK) res = fail(SV_EDEVICE, "host tier stream failed");
+    for (int b = 0; b < 2; b++) {
+        if (hs[b]) (void)sv_free(hs[b]);
+        if (dbuf[b]) (void)hipFree(dbuf[b]);
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t q : {s_in, s_comp, s_out})
+        if (q) (void)hipStreamDestroy(q);
+    if (res != SV_OK) g_err = err;
+    if (res == SV_OK && stats) {
+        stats->bytes_h2d = (double)hp.size() * (double)n_chunks * (double)chunk_bytes;
+        stats->bytes_d2h = stats->bytes_h2d;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return res;
 }
 
 sv_status sv_norm2(sv_state s, double* out)

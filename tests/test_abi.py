@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every function that
 include/sv.h declares, rejects bad arguments before touching a device, and
 plans circuits (sv_plan is host-only)."""
+import collections
 import ctypes
 import os
 import re
@@ -35,6 +36,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(B.SvGate) == 4 * 8 + 8 * 3 + 8 * 32
     assert ctypes.sizeof(B.SvPauli) == 24
     assert ctypes.sizeof(B.SvDiff) == 48
+    assert ctypes.sizeof(B.SvHostStats) == 4 * 8 + 3 * 8
 
 
 def status(fn, *args):
@@ -54,6 +56,28 @@ def test_alloc_argument_errors_return_before_any_device_call():
     assert L.sv_alloc(ctypes.byref(h), 4, B.SV_C128, ctypes.c_void_p(4104), 256, None) == B.SV_EINVAL
     assert b"aligned" in L.sv_last_error()
     assert not h.value
+
+
+def test_host_apply_argument_errors_return_before_any_copy():
+    """sv_host_apply validates everything before it touches the host state or
+    the GPU (the pointer below is never dereferenced)."""
+    L = B.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    one = B.gate_array([C.gate("h", 3)])
+    st = B.SvHostStats()
+    assert L.sv_host_apply(None, 10, B.SV_C128, one, 1, 6, ctypes.byref(st)) == B.SV_EINVAL
+    assert L.sv_host_apply(ctypes.c_void_p((1 << 20) + 8), 10, B.SV_C128, one, 1, 6, None) == B.SV_EINVAL
+    assert b"aligned" in L.sv_last_error()
+    assert L.sv_host_apply(fake, 0, B.SV_C128, one, 1, 6, None) == B.SV_EINVAL
+    assert L.sv_host_apply(fake, 10, B.SV_C128, one, 1, 0, None) == B.SV_EINVAL
+    assert L.sv_host_apply(fake, 10, 5, one, 1, 6, None) == B.SV_EINVAL
+    assert L.sv_host_apply(fake, 3, B.SV_C128, one, 1, 2, None) == B.SV_EINVAL  # qubit 3 >= n
+    # a chunk of 4 of 20 qubits has 2 free high qubits: a gate on 3 high qubits cannot fit
+    CtrlGate = collections.namedtuple("CtrlGate", "op qubits params param_index controls")
+    big = B.gate_array([CtrlGate("x", (17,), (), -1, (18, 19))])
+    assert L.sv_host_apply(fake, 20, B.SV_C128, big, 1, 4, ctypes.byref(st)) == B.SV_EUNSUPPORTED
+    assert L.sv_host_apply(fake, 20, B.SV_C128, one, 0, 8, ctypes.byref(st)) == B.SV_OK  # nothing to do
+    assert st.n_passes == 0 and st.chunk_qubits == 8 and st.n_chunks == 1 << 12
 
 
 def test_null_handle_errors():
