@@ -554,7 +554,16 @@ struct HostPass {
     std::vector<sv_gate> gates;     // gates with qubits renumbered to chunk positions
 };
 
-int host_high_qubits(int n, int c) { return std::min(std::min(8, c / 2), n - c); }
+// High local qubits of a chunk: up to 8 (runs of 2^(c-8) amplitudes stay
+// large DMA copies), none when the chunk is the whole state.
+int host_high_qubits(int n, int c)
+{
+    if (n == c) return 0;
+    int h = 8;
+    const char* e = std::getenv("QVEC_HOST_HIGH");  // override (measurement knob)
+    if (e && std::atoi(e) >= 1 && std::atoi(e) <= 12) h = std::atoi(e);
+    return std::min(h, c / 2);
+}
 
 sv_status plan_host_passes(int n, int c, const sv_gate* gates, int n_gates, std::vector<HostPass>* out)
 {
