@@ -565,21 +565,48 @@ int host_high_qubits(int n, int c)
     return std::min(h, c / 2);
 }
 
-sv_status plan_host_passes(int n, int c, const sv_gate* gates, int n_gates, std::vector<HostPass>* out)
+sv_status plan_host_passes(int n, int c, const sv_gate* gates, const std::vector<HostGate>& hg,
+                           std::vector<HostPass>* out)
 {
+    // Each pass scans the pending gates in order and takes every gate whose
+    // qubits fit in the chunk (the low qubits plus up to h high ones, chosen
+    // as the scan meets them) and that commutes with the gates it skips (on
+    // each shared qubit both act diagonally), as the device planner does for
+    // blocks; the taken gates keep their order.
     const int h = host_high_qubits(n, c), m = c - h;
+    const uint64_t low = m >= 64 ? ~0ull : ((1ull << m) - 1);
+    const size_t ng = hg.size();
+    std::vector<char> done(ng, 0);
+    size_t first = 0;
     out->clear();
-    HostPass cur;
-    uint64_t high = 0;
-    auto close = [&]() {
+    while (true) {
+        while (first < ng && done[first]) first++;
+        if (first >= ng) break;
+        HostPass cur;
+        uint64_t high = 0, blk_dense = 0, blk_diag = 0;
+        for (size_t i = first; i < ng; i++) {
+            if (done[i]) continue;
+            const uint64_t dn = dense_bits(hg[i]), dg = diag_bits(hg[i]);
+            const uint64_t add = (dn | dg) & ~low & ~high;
+            const bool free = !(dn & (blk_dense | blk_diag)) && !(dg & blk_dense);
+            if (free && __builtin_popcountll(high | add) <= h) {
+                high |= add;
+                cur.gates.push_back(gates[i]);
+                done[i] = 1;
+            } else {
+                blk_dense |= dn;
+                blk_diag |= dg;
+            }
+        }
+        if (cur.gates.empty())
+            return fail(SV_EUNSUPPORTED, "gate " + std::to_string(first) + " needs more high qubits than a chunk holds");
         // fill the high set to h qubits (lowest first) so that every chunk has 2^c amplitudes
         for (int q = m; q < n && __builtin_popcountll(high) < h; q++) high |= 1ull << q;
-        cur.high.clear();
         for (int q = m; q < n; q++)
             if (high >> q & 1) cur.high.push_back(q);
         int pos[64];
         for (int q = 0; q < 64; q++) pos[q] = q < m ? q : -1;
-        for (int i = 0; i < h; i++) pos[cur.high[i]] = m + i;
+        for (int k = 0; k < h; k++) pos[cur.high[k]] = m + k;
         for (sv_gate& g : cur.gates) {
             const bool two = g.op == SV_OP_MATRIX2 || g.op == SV_OP_CNOT || g.op == SV_OP_CZ || g.op == SV_OP_CP ||
                              g.op == SV_OP_SWAP;
@@ -587,27 +614,8 @@ sv_status plan_host_passes(int n, int c, const sv_gate* gates, int n_gates, std:
             if (two) g.qubits[1] = pos[g.qubits[1]];
             for (int k = 0; k < g.n_controls; k++) g.controls[k] = pos[g.controls[k]];
         }
-        out->push_back(cur);
-        cur = HostPass{};
-        high = 0;
-    };
-    for (int i = 0; i < n_gates; i++) {
-        const sv_gate& g = gates[i];
-        const bool two = g.op == SV_OP_MATRIX2 || g.op == SV_OP_CNOT || g.op == SV_OP_CZ || g.op == SV_OP_CP ||
-                         g.op == SV_OP_SWAP;
-        uint64_t need = 1ull << g.qubits[0];
-        if (two) need |= 1ull << g.qubits[1];
-        for (int k = 0; k < g.n_controls; k++) need |= 1ull << g.controls[k];
-        const uint64_t low = m >= 64 ? ~0ull : ((1ull << m) - 1);
-        const uint64_t add = need & ~low & ~high;
-        if (__builtin_popcountll(high | add) > h) {
-            if (cur.gates.empty()) return fail(SV_EUNSUPPORTED, "gate " + std::to_string(i) + " needs more high qubits than a chunk holds");
-            close();
-        }
-        high |= need & ~low;
-        cur.gates.push_back(g);
+        out->push_back(std::move(cur));
     }
-    if (!cur.gates.empty()) close();
     return SV_OK;
 }
 
@@ -823,7 +831,7 @@ sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv
     if (st != SV_OK) return st;
     const int n = n_qubits, c = std::min(chunk_qubits, n_qubits);
     std::vector<HostPass> hp;
-    st = plan_host_passes(n, c, gates, n_gates, &hp);
+    st = plan_host_passes(n, c, gates, hg, &hp);
     if (st != SV_OK) return st;
     const int h = host_high_qubits(n, c), m = c - h;
     const uint64_t n_chunks = 1ull << (n - c), n_runs = 1ull << h;
