@@ -179,7 +179,7 @@ def timed(fn, reps=1):
     return (time.perf_counter() - t0) / reps, r
 
 
-def host_tier(qv, n=30, chunk=27, depth=4):
+def host_tier(qv, n=30, chunk=28, depth=4):
     """Out-of-core tier: the random U3 + CNOT circuit on a complex128 state in
     pinned host memory, chunks of 2^chunk amplitudes through the GPU. The
     state is allocated and set outside the timed call; the call's own clock
