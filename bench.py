@@ -282,6 +282,10 @@ def main() -> int:
                     help="only time the library's streaming copy kernel on two state-sized buffers")
     ap.add_argument("--sweeps", action="store_true",
                     help="only time one unfused U3 sweep per target qubit (the one-qubit sweep kernel)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only the 24-qubit ansatz forward and adjoint figures (no parameter shift)")
+    ap.add_argument("--host-tier", action="store_true",
+                    help="only the host tier on a 30-qubit complex128 state in pinned host memory")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -299,6 +303,12 @@ def main() -> int:
         return copy_probe(qv, B, n, dtype, elem, args.steps)
     if args.sweeps:
         print(json.dumps({"sweeps": sweep_rates(qv, B, n, dtype, elem, args.steps)}), flush=True)
+        return 0
+    if args.adjoint:
+        print(json.dumps({"adjoint": adjoint_figures(qv, shift_evals=False)}), flush=True)
+        return 0
+    if args.host_tier:
+        print(json.dumps({"host_tier": host_tier(qv)}), flush=True)
         return 0
     rand, x, qft = workload(n)
     gates_per_step = len(rand) + len(qft)
