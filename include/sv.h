@@ -192,8 +192,10 @@ sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gate
  * torch tensor with pin_memory), 16-byte aligned, read and written in place.
  * A chunk is the 2^c indices (c = min(chunk_qubits, n)) that agree outside
  * the lowest c - h qubits (contiguous runs) and h high qubits chosen per
- * pass; gates are taken in order while every qubit of each (targets and
- * controls) lies in the chunk, and each chunk of a pass goes host -> device,
+ * pass; a pass takes every gate whose qubits (targets and controls) lie in
+ * the chunk and that commutes with the gates it leaves for later passes (on
+ * each shared qubit both act diagonally), so the result equals applying the
+ * gates in order; each chunk of a pass goes host -> device,
  * through the fused device path (as sv_apply_fused on a c-qubit state) and
  * back. Two device buffers of 2^c * S_state bytes are allocated for the call
  * and freed before it returns; copies in, passes and copies out of three

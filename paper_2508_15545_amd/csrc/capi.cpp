@@ -543,9 +543,9 @@ sv_status pauli_apply_impl(sv_state s, const T* psi, T* dst, const std::vector<T
 // blocks are written back). A chunk is the set of 2^c indices that agree
 // outside c local qubits: the lowest m = c - h qubits (contiguous runs of 2^m
 // amplitudes) and h high qubits chosen per pass, so one chunk is 2^h runs.
-// Gates are taken in order while all their qubits (targets and controls) fit
-// in the pass's local set; each chunk is then a c-qubit state for the device
-// planner. Two device buffers and three streams overlap the copy-in of one
+// A pass takes the gates whose qubits (targets and controls) fit in its
+// chunk and that commute with the gates it leaves for later; each chunk is
+// then a c-qubit state for the device planner. Two device buffers and three streams overlap the copy-in of one
 // chunk, the passes over another and the copy-out of a third.
 namespace {
 
