@@ -1,0 +1,60 @@
+"""The planner's block passes executed on the host (tests/plan_emulator.cpp):
+the load and store mappings, op positions, controls and phase-op encodings as
+the register kernel reads them give the same state as applying the gates one
+by one, and the structural rules the kernel relies on hold (within-wave
+exchanges keep each wave's indices; with no workgroup-wide exchange a wave
+stores only where it loaded; a pass stores from the mapping it is in). Runs
+on the CPU; plans with and without qubit moves between passes."""
+import os
+import subprocess
+
+import pytest
+
+import circuits as C
+from paper_2508_15545_amd import _binding as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2508_15545_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def emulator(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("emu") / "plan_emulator")
+    cmd = ["g++", "-O2", "-std=c++17", "-w", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", f"-I{CSRC}",
+           "-o", exe, os.path.join(HERE, "plan_emulator.cpp"), os.path.join(CSRC, "planner.cpp"),
+           os.path.join(CSRC, "gates.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail("emulator build failed:\n" + r.stderr[-2000:])
+    return exe
+
+
+def gate_lines(circ):
+    out = []
+    for g in circ:
+        q = list(g.qubits) + [0]
+        a = list(g.params) + [0.0, 0.0, 0.0]
+        out.append(f"{B.OPS[g.op]} {q[0]} {q[1]} {a[0]!r} {a[1]!r} {a[2]!r}")
+    return "\n".join(out) + "\n"
+
+
+CASES = [
+    ("cx", 17, 8, 0), ("cx", 18, 10, 1), ("cx", 20, 10, 0), ("cx", 20, 10, 1), ("cx", 20, 10, 2),
+    ("cz", 19, 8, 3), ("qft", 16, 0, 0), ("qft", 19, 0, 0), ("hea", 15, 4, 0),
+]
+
+
+@pytest.mark.parametrize("park", [0, 1])
+@pytest.mark.parametrize("elem", [16, 8])
+@pytest.mark.parametrize("kind,n,depth,seed", CASES)
+def test_planned_passes_equal_gate_by_gate(emulator, kind, n, depth, seed, elem, park):
+    if kind == "qft":
+        circ = C.qft(n)
+    elif kind == "hea":
+        circ = C.hea(n, depth, C.hea_params(n, depth, seed))
+    else:
+        circ = C.random_u3_layers(n, depth, seed, entangler=kind)
+    r = subprocess.run([emulator, str(n), str(elem), str(park)], input=gate_lines(circ), capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "structure_errors=0" in r.stdout
