@@ -12,6 +12,7 @@ module) and observables as ``(coeff, x_mask, z_mask)`` triples.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Iterable, Optional, Sequence
@@ -101,6 +102,8 @@ def lib():
         L.or_reset_pair_updates.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -194,6 +197,14 @@ def run(circuit: Sequence, n: int, x0: int = 0, state: Optional[np.ndarray] = No
     return s
 
 
+def run_inplace(state: np.ndarray, n: int, circuit: Sequence) -> np.ndarray:
+    """Apply ``circuit`` gate by gate to ``state`` itself (no copy)."""
+    _check_state(state, n)
+    if circuit and lib().or_run(state.ctypes.data, n, _gates(circuit), len(circuit)):
+        raise ValueError("bad circuit")
+    return state
+
+
 def run_inverse(circuit: Sequence, n: int, state: np.ndarray) -> np.ndarray:
     s = np.array(state, dtype=np.complex128, copy=True)
     _check_state(s, n)
@@ -273,3 +284,22 @@ def reset_pair_updates() -> None:
 def num_threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(lib().or_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Run the oracle's OpenMP loops on k threads from now on."""
+    lib().or_set_threads(int(k))
+
+
+def qft_basis_amplitudes(n: int, x: int, lo: int, hi: int) -> np.ndarray:
+    """Amplitudes lo .. hi-1 of the quantum Fourier transform of the basis
+    state e_x (the definition of the transform that the textbook circuit of
+    H and controlled phases realises, qubit n-1 most significant):
+    alpha_y = 2^(-n/2) exp(2 pi i ((x y) mod 2^n) / 2^n). The phase numerator
+    is formed in exact integer arithmetic, so each amplitude carries one
+    rounding of the angle and one complex exponential."""
+    if not (0 <= x < (1 << n) and 0 <= lo <= hi <= (1 << n)) or n > 31:
+        raise ValueError("need 0 <= x < 2^n, 0 <= lo <= hi <= 2^n, n <= 31")
+    y = np.arange(lo, hi, dtype=np.uint64)
+    num = (np.uint64(x) * y) & np.uint64((1 << n) - 1)  # x y < 2^62: exact
+    return np.exp(2j * np.pi * (num.astype(np.float64) / float(1 << n))) / math.sqrt(1 << n)

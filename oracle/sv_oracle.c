@@ -227,8 +227,10 @@ void or_set_basis(cplx* s, int n, uint64_t x)
 
 /* ---------------------------------------------------------- reductions --- */
 
-/* Pairwise (cascade) summation of v[0..len). */
-double or_pairwise_sum(const double* v, int64_t len)
+/* Pairwise (cascade) summation of v[0..len): a range of more than 8 terms
+ * is the sum of its two halves (the first has len / 2 terms), 8 or fewer
+ * are added left to right. */
+static double pairwise_rec(const double* v, int64_t len)
 {
     if (len <= 8) {
         double t = 0;
@@ -236,7 +238,36 @@ double or_pairwise_sum(const double* v, int64_t len)
         return t;
     }
     const int64_t h = len / 2;
-    return or_pairwise_sum(v, h) + or_pairwise_sum(v + h, len - h);
+    return pairwise_rec(v, h) + pairwise_rec(v + h, len - h);
+}
+
+/* The same tree for long ranges, with the 64 subtrees six levels down
+ * summed on OpenMP threads and then joined in the tree's own order: every
+ * node is still the sum of its two children, so the result is identical to
+ * pairwise_rec's. */
+double or_pairwise_sum(const double* v, int64_t len)
+{
+    enum { DEPTH = 6, LEAVES = 1 << DEPTH };
+    if (len < ((int64_t)1 << 16)) return pairwise_rec(v, len);
+    int64_t off[LEAVES], cnt[LEAVES];
+    off[0] = 0;
+    cnt[0] = len;
+    for (int d = 0; d < DEPTH; d++) {      /* split every node of level d */
+        const int nodes = 1 << d;
+        for (int k = nodes - 1; k >= 0; k--) {
+            const int64_t o = off[k], c = cnt[k], h = c / 2;
+            off[2 * k] = o;
+            cnt[2 * k] = h;
+            off[2 * k + 1] = o + h;
+            cnt[2 * k + 1] = c - h;
+        }
+    }
+    double part[LEAVES];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < LEAVES; k++) part[k] = pairwise_rec(v + off[k], cnt[k]);
+    for (int nodes = LEAVES / 2; nodes >= 1; nodes /= 2)   /* join level by level */
+        for (int k = 0; k < nodes; k++) part[k] = part[2 * k] + part[2 * k + 1];
+    return part[0];
 }
 
 /* P|j> for the Pauli string (x_mask, z_mask): i^{#Y} (-1)^{|j & z|} |j ^ x>. */
@@ -417,6 +448,8 @@ int or_finite_diff_grad(int n, uint64_t x0, const or_gate* gates, int n_gates,
 #ifdef _OPENMP
 #include <omp.h>
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int k) { if (k > 0) omp_set_num_threads(k); }
 #else
 int or_num_threads(void) { return 1; }
+void or_set_threads(int k) { (void)k; }
 #endif

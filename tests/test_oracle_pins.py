@@ -117,6 +117,81 @@ def test_two_qubit_truth_tables():
                                oracle.gate_matrix(C.gate("cz", 0, 1)), atol=1e-15)
 
 
+def test_mat1_decode_is_row_major_closed_form():
+    """A MATRIX1 gate reads its 2x2 matrix row-major as (re, im) pairs: the
+    non-symmetric [[0, 1], [i, 0]] sends |0> to i|1> and |1> to |0> on its
+    qubit (its transpose would send |0> to |1>)."""
+    u = np.array([[0, 1], [1j, 0]], dtype=np.complex128)
+    g = C.gate("mat1", 2, params=C.matrix_params(u))
+    np.testing.assert_array_equal(oracle.gate_matrix(g), u)
+    n = 4
+    for x in range(1 << n):
+        want = np.zeros(1 << n, dtype=np.complex128)
+        want[x ^ 4] = 1.0 if (x >> 2) & 1 else 1j
+        np.testing.assert_array_equal(oracle.run([g], n, x0=x), want)
+
+
+# A phased 4-cycle on the two-qubit basis m = bit(t0) + 2 bit(t1):
+# |m> -> PH[m] |PERM[m]>. It is neither symmetric nor invariant under
+# exchanging t0 and t1, so a transposed decode or a swapped index order
+# sends some basis state elsewhere.
+PERM4 = (1, 3, 0, 2)
+PH4 = (1.0, 1j, -1.0, -1j)
+
+
+def phased_cycle_4x4():
+    m = np.zeros((4, 4), dtype=np.complex128)
+    for c in range(4):
+        m[PERM4[c], c] = PH4[c]
+    return m
+
+
+@pytest.mark.parametrize("t0,t1", [(3, 1), (0, 4), (4, 0)])
+def test_mat2_decode_closed_form(t0, t1):
+    u = phased_cycle_4x4()
+    g = C.gate("mat2", t0, t1, params=C.matrix_params(u))
+    np.testing.assert_array_equal(oracle.gate_matrix(g), u)
+    n = 5
+    for x in range(1 << n):
+        m = ((x >> t0) & 1) + 2 * ((x >> t1) & 1)
+        r = PERM4[m]
+        y = (x & ~((1 << t0) | (1 << t1))) | ((r & 1) << t0) | ((r >> 1) << t1)
+        want = np.zeros(1 << n, dtype=np.complex128)
+        want[y] = PH4[m]
+        np.testing.assert_array_equal(oracle.run([g], n, x0=x), want)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_matrix_gates_against_dense_products_of_their_matrices(seed):
+    """MATRIX1 / MATRIX2 gates against Eq. 3-4 built from the unitary itself
+    (not from the oracle's decode of it)."""
+    n = 6
+    rng = C.rng_for(40 + seed)
+    s0 = C.random_state(n, seed)
+    for k in range(n):
+        u = C.random_unitary(2, rng)
+        got = oracle.run([C.gate("mat1", k, params=C.matrix_params(u))], n, state=s0)
+        np.testing.assert_allclose(got, kron_1q(u, k, n) @ s0, atol=1e-13)
+    for a, b in [(0, 5), (5, 0), (2, 3), (4, 1)]:
+        u4 = C.random_unitary(4, rng)
+        got = oracle.run([C.gate("mat2", a, b, params=C.matrix_params(u4))], n, state=s0)
+        np.testing.assert_allclose(got, tensordot_2q(s0, u4, a, b, n), atol=1e-13)
+
+
+def test_tensordot_reference_orientation():
+    """The dense two-qubit reference itself: CNOT as a 4x4 in the basis
+    bit(t0) + 2 bit(t1) (control t0) flips t1 exactly where t0 is set."""
+    n = 4
+    cx = np.zeros((4, 4))
+    for m in range(4):
+        cx[m ^ (2 if m & 1 else 0), m] = 1
+    for x in range(1 << n):
+        e = np.zeros(1 << n, dtype=np.complex128)
+        e[x] = 1
+        got = tensordot_2q(e, cx, 1, 3, n)
+        assert got[x ^ (8 if (x >> 1) & 1 else 0)] == 1 and abs(got).sum() == 1
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_all_matrices_unitary(seed):
     for g in C.random_mixed_circuit(3, 40, seed):
@@ -208,7 +283,8 @@ def test_ghz(n):
 
 
 def qft_closed_form(n, x, ys):
-    """alpha_y = 2^(-n/2) exp(2 pi i ((x y) mod 2^n) / 2^n), exact integer phase."""
+    """alpha_y = 2^(-n/2) exp(2 pi i ((x y) mod 2^n) / 2^n), exact integer phase
+    (Python integers, one term at a time)."""
     N = 1 << n
     ph = np.array([(x * int(y)) % N for y in ys], dtype=np.float64) / N
     return np.exp(2j * np.pi * ph) / math.sqrt(N)
@@ -223,6 +299,34 @@ def test_qft_of_basis_state(n, seed):
         e = np.zeros(1 << n)
         e[x] = 1
         np.testing.assert_allclose(s, np.fft.ifft(e) * math.sqrt(1 << n), atol=1e-12)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (5, 1), (10, 2), (13, 3)])
+def test_oracle_qft_amplitudes_against_circuit_and_fft(n, seed):
+    """The oracle's QFT amplitudes (used for every amplitude of the 29-qubit
+    check) against the gate-by-gate QFT circuit, numpy's FFT and the
+    per-term closed form, also over sub-ranges."""
+    x = C.random_basis_index(n, seed)
+    N = 1 << n
+    amp = oracle.qft_basis_amplitudes(n, x, 0, N)
+    np.testing.assert_allclose(amp, oracle.run(C.qft(n), n, x0=x), atol=1e-12)
+    e = np.zeros(N)
+    e[x] = 1
+    np.testing.assert_allclose(amp, np.fft.ifft(e) * math.sqrt(N), atol=1e-12)
+    lo, hi = N // 3, N // 3 + max(1, N // 4)
+    np.testing.assert_allclose(oracle.qft_basis_amplitudes(n, x, lo, hi), qft_closed_form(n, x, range(lo, hi)),
+                               atol=1e-15)
+
+
+def test_oracle_qft_amplitudes_large_n_exact_phase():
+    """At 29 qubits x y reaches 2^58: the integer phase must stay exact
+    (Python integers as the reference)."""
+    n = 29
+    x = C.random_basis_index(n, 0)
+    ys = [0, 1, 2, (1 << n) - 1, (1 << n) - 2, 123456789, (1 << 28) + 17]
+    for y in ys:
+        got = oracle.qft_basis_amplitudes(n, x, y, y + 1)[0]
+        assert abs(got - qft_closed_form(n, x, [y])[0]) <= 1e-18
 
 
 def test_qft_gate_count():
@@ -255,6 +359,26 @@ def test_random_u3_layers_shape():
 def test_pairwise_sum_matches_fsum():
     v = C.rng_for(1).standard_normal(100003) * 1e3
     assert abs(oracle.pairwise_sum(v) - math.fsum(v)) < 1e-8
+
+
+def _pairwise_tree(v, lo, n):
+    if n <= 8:
+        t = 0.0
+        for i in range(lo, lo + n):
+            t += float(v[i])
+        return t
+    h = n // 2
+    return _pairwise_tree(v, lo, h) + _pairwise_tree(v, lo + h, n - h)
+
+
+@pytest.mark.parametrize("n", [7, 1000, 65535, 65536, 100003])
+def test_pairwise_sum_is_the_halving_tree(n):
+    """The oracle sums long ranges on threads; the result must be the plain
+    halving tree's, bit for bit (values over ten decades, so that a changed
+    order would show)."""
+    rng = C.rng_for(n)
+    v = rng.standard_normal(n) * 10.0 ** rng.integers(-5, 6, n)
+    assert oracle.pairwise_sum(v) == _pairwise_tree(v, 0, n)
 
 
 @pytest.mark.parametrize("n", [3, 8])
