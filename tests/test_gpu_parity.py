@@ -428,3 +428,63 @@ def test_timing_counts_launches(qv):
     launches, ms = st.timing_read(B.KF_BLOCK)
     assert launches >= 1 and ms > 0
     assert st.timing_read(B.KF_INIT)[0] == 1
+
+
+# ------------------------------------------------------------ matrix layout ---
+
+PERM4 = (1, 3, 0, 2)
+PH4 = (1.0, 1j, -1.0, -1j)
+
+
+def phased_cycle_4x4():
+    """|m> -> PH4[m] |PERM4[m]> on the basis m = bit(t0) + 2 bit(t1): neither
+    symmetric nor invariant under exchanging t0 and t1."""
+    m = np.zeros((4, 4), dtype=np.complex128)
+    for c in range(4):
+        m[PERM4[c], c] = PH4[c]
+    return m
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fused", [False, True])
+def test_matrix_layout_closed_form(qv, dtype, fused):
+    """MATRIX1 / MATRIX2 read row-major (re, im) pairs with the two-qubit
+    index bit(t0) + 2 bit(t1): [[0, 1], [i, 0]] sends |0> to i|1> and |1> to
+    |0> on its qubit, and the phased 4-cycle sends each basis state to one
+    known basis state with a known phase. Exact for both dtypes (every entry
+    is 0, +-1 or +-i), on qubits inside and outside one block."""
+    n = 14
+    u1 = np.array([[0, 1], [1j, 0]], dtype=np.complex128)
+    u4 = phased_cycle_4x4()
+    xs = [0, 1, (1 << n) - 1, 0x2A5C, C.random_basis_index(n, 4)]
+    for q in (0, 5, 13):
+        g = C.gate("mat1", q, params=C.matrix_params(u1))
+        for x in xs:
+            st = qv.State(n, dtype).set_basis(x).apply([g], fused=fused)
+            want = np.zeros(1 << n, dtype=np.complex128)
+            want[x ^ (1 << q)] = 1.0 if (x >> q) & 1 else 1j
+            assert np.array_equal(host(st), want), (q, x)
+    for t0, t1 in ((3, 1), (0, 13), (13, 0), (12, 6)):
+        g = C.gate("mat2", t0, t1, params=C.matrix_params(u4))
+        for x in xs:
+            m = ((x >> t0) & 1) + 2 * ((x >> t1) & 1)
+            r = PERM4[m]
+            y = (x & ~((1 << t0) | (1 << t1))) | ((r & 1) << t0) | ((r >> 1) << t1)
+            want = np.zeros(1 << n, dtype=np.complex128)
+            want[y] = PH4[m]
+            st = qv.State(n, dtype).set_basis(x).apply([g], fused=fused)
+            assert np.array_equal(host(st), want), (t0, t1, x)
+
+
+def test_autograd_function_complex64(qv):
+    """The autograd path in complex64: FP32 state, FP64 expectation and
+    gradient accumulation, against the oracle's FP64 adjoint."""
+    n, layers = 10, 3
+    th = torch.tensor(C.hea_params(n, layers, seed=6), dtype=torch.float64, requires_grad=True)
+    circ = C.hea(n, layers, th.detach().numpy())
+    H = C.zz_x_chain(n)
+    f = qv.expectation(th, circ, H, n, torch.complex64)
+    (2.0 * f).backward()
+    f_o, g_o = oracle.adjoint_grad(circ, n, H, th.numel())
+    assert abs(f.item() - f_o) <= 1e-5
+    assert np.max(np.abs(th.grad.numpy() - 2.0 * g_o)) <= 1e-4
