@@ -215,6 +215,27 @@ sv_status sv_norm2(sv_state s, double* out);
  * Errors: SV_EINVAL if a mask has bits >= n. */
 sv_status sv_expect(sv_state s, const sv_pauli* terms, int n_terms, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * expectation of sv_expect on a raw device state, with no handle and no
+ * allocation. Enqueues on hip_stream (NULL = default stream) of the current
+ * device, which must hold state and d_out, and returns without waiting.
+ *   state   2^n_qubits amplitudes of dtype, device memory, 16-byte aligned
+ *   terms   n_terms Pauli strings (host, read during the call); the terms
+ *           form batches of up to 16 terms sharing one x_mask, at most 64
+ *   d_out   one double in device memory (8-byte aligned): on completion it
+ *           holds <psi|H|psi>, bit-identical to what sv_expect returns for
+ *           the same state and terms (same launches, same order of sums)
+ * Its scratch is a fixed 1 MiB device array per GPU (64 batches x 2048
+ * partial sums, then 64 batch sums), held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (on
+ * different streams, or from different threads) race on it and must be
+ * ordered by the caller. Errors: SV_EINVAL (bad dtype, n_qubits, pointer,
+ * alignment, mask >= 2^n, non-finite coefficient, more than 64 batches),
+ * SV_EDEVICE; on an error nothing is enqueued. */
+sv_status sv_expect_noalloc(const void* state, int n_qubits, sv_dtype dtype, const sv_pauli* terms,
+                            int n_terms, double* d_out, void* hip_stream);
+
 /* dst = H psi (same dtype and size as s; dst_buf is caller device memory of
  * >= 2^n * S_state bytes, not overlapping the state). Enqueue only. */
 sv_status sv_apply_pauli_sum(sv_state s, const sv_pauli* terms, int n_terms, void* dst_buf,

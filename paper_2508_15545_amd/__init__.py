@@ -20,7 +20,7 @@ import torch
 from . import _binding as B
 from ._binding import SvError, check, gate_array, lib, pauli_array
 
-__all__ = ["State", "SvError", "plan_stats", "expectation", "Expectation", "copy"]
+__all__ = ["State", "SvError", "plan_stats", "expectation", "Expectation", "copy", "expect_noalloc"]
 
 _DTYPES = {torch.complex128: B.SV_C128, torch.complex64: B.SV_C64}
 
@@ -157,6 +157,25 @@ def copy(state: State, dst: torch.Tensor, src: torch.Tensor) -> None:
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst too small")
     check(lib().sv_copy(state.handle, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes))
+
+
+def expect_noalloc(state: torch.Tensor, terms, out: torch.Tensor) -> torch.Tensor:
+    """<psi|H|psi> of a state tensor into out (a one-element float64 tensor
+    on the state's device) through sv_expect_noalloc: enqueued on the current
+    stream, no allocation by the library, no wait."""
+    if state.dtype not in _DTYPES or state.device.type != "cuda" or not state.is_contiguous():
+        raise ValueError("state must be a contiguous complex64/complex128 GPU tensor")
+    n = state.numel().bit_length() - 1
+    if state.numel() != 1 << n:
+        raise ValueError("state must have 2^n entries")
+    if out.dtype != torch.float64 or out.device != state.device or out.numel() < 1:
+        raise ValueError("out must be a float64 tensor on the state's device")
+    terms = list(terms)
+    with torch.cuda.device(state.device):
+        check(lib().sv_expect_noalloc(ctypes.c_void_p(state.data_ptr()), n, _DTYPES[state.dtype],
+                                      pauli_array(terms), len(terms), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(state.device)))
+    return out
 
 
 def host_apply(state: torch.Tensor, circuit, chunk_qubits: int) -> dict:

@@ -90,6 +90,7 @@ SIGNATURES = {
     "sv_host_apply": (_st, [_vp, _i, _i, ctypes.POINTER(SvGate), _i, _i, ctypes.POINTER(SvHostStats)]),
     "sv_norm2": (_st, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "sv_expect": (_st, [_vp, ctypes.POINTER(SvPauli), _i, ctypes.POINTER(ctypes.c_double)]),
+    "sv_expect_noalloc": (_st, [_vp, _i, _i, ctypes.POINTER(SvPauli), _i, _vp, _vp]),
     "sv_apply_pauli_sum": (_st, [_vp, ctypes.POINTER(SvPauli), _i, _vp, ctypes.c_size_t]),
     "sv_adjoint_grad": (_st, [_vp, ctypes.POINTER(SvGate), _i, ctypes.POINTER(SvPauli), _i, _vp, ctypes.c_size_t,
                               ctypes.POINTER(ctypes.c_double), _i, ctypes.POINTER(ctypes.c_double)]),

@@ -5,7 +5,7 @@
 #include <cstdlib>
 #include <chrono>
 #include <cstring>
-#include <map>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -237,38 +237,42 @@ sv_status check_terms(sv_state s, const sv_pauli* terms, int n_terms)
 }
 
 // Terms grouped by x mask (first-appearance order), at most kTermsPerLaunch
-// per batch; coefficients carry i^{#Y}.
+// per batch, terms of one mask in their input order; coefficients carry
+// i^{#Y}. Each batch is handed to f as it is formed, with no heap
+// allocation (the non-allocating expectation uses this too); a mask is
+// grouped where it first appears, so the scan is quadratic in n_terms.
+template <typename F>
+void visit_batches(const sv_pauli* terms, int n_terms, F&& f)
+{
+    static const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+    for (int t = 0; t < n_terms; t++) {
+        const uint64_t x = terms[t].x_mask;
+        bool seen = false;
+        for (int u = 0; u < t && !seen; u++) seen = terms[u].x_mask == x;
+        if (seen) continue;
+        TermBatch tb{};
+        tb.x_mask = x;
+        for (int u = t; u < n_terms; u++) {
+            const sv_pauli& p = terms[u];
+            if (p.x_mask != x) continue;
+            const int ny = __builtin_popcountll(p.x_mask & p.z_mask) & 3;
+            tb.z_mask[tb.n_terms] = p.z_mask;
+            tb.coeff_re[tb.n_terms] = p.coeff * re[ny];
+            tb.coeff_im[tb.n_terms] = p.coeff * im[ny];
+            if (++tb.n_terms == kTermsPerLaunch) {
+                f(tb);
+                tb = TermBatch{};
+                tb.x_mask = x;
+            }
+        }
+        if (tb.n_terms > 0) f(tb);
+    }
+}
+
 std::vector<TermBatch> batch_terms(const sv_pauli* terms, int n_terms)
 {
     std::vector<TermBatch> out;
-    std::map<uint64_t, std::vector<int>> by_x;
-    std::vector<uint64_t> order;
-    for (int t = 0; t < n_terms; t++) {
-        auto it = by_x.find(terms[t].x_mask);
-        if (it == by_x.end()) {
-            order.push_back(terms[t].x_mask);
-            by_x[terms[t].x_mask].push_back(t);
-        } else {
-            it->second.push_back(t);
-        }
-    }
-    for (uint64_t x : order) {
-        const std::vector<int>& idx = by_x[x];
-        for (size_t k = 0; k < idx.size(); k += kTermsPerLaunch) {
-            TermBatch tb{};
-            tb.x_mask = x;
-            for (size_t j = k; j < idx.size() && j < k + kTermsPerLaunch; j++) {
-                const sv_pauli& p = terms[idx[j]];
-                const int ny = __builtin_popcountll(p.x_mask & p.z_mask) & 3;
-                static const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
-                tb.z_mask[tb.n_terms] = p.z_mask;
-                tb.coeff_re[tb.n_terms] = p.coeff * re[ny];
-                tb.coeff_im[tb.n_terms] = p.coeff * im[ny];
-                tb.n_terms++;
-            }
-            out.push_back(tb);
-        }
-    }
+    visit_batches(terms, n_terms, [&](const TermBatch& tb) { out.push_back(tb); });
     return out;
 }
 
@@ -1227,6 +1231,90 @@ sv_status sv_timing_read(sv_state s, int kernel, int64_t* launches, double* tota
     if (st != SV_OK) return st;
     *launches = s->acc_n[kernel];
     *total_ms = s->acc_ms[kernel];
+    return SV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- non-allocating calls ---
+// sv_expect_noalloc keeps its reduction scratch (per-block partials of each
+// term batch, then one sum per batch) in a fixed device array instead of
+// buffers the library allocates: one copy per GPU, held until the process
+// ends, shared by every call on that GPU.
+namespace {
+
+constexpr int kNoAllocMaxBatches = 64;
+constexpr size_t kNoAllocScratchDoubles = (size_t)kNoAllocMaxBatches * kReduceBlocks + kNoAllocMaxBatches;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current GPU's copy of `scratch`, looked up once
+// per device with that device current. Host code passes this address to
+// kernels; the array's name is only a host-side stand-in.
+sv_status scratch_for_device(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(SV_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_expect_noalloc(const void* state, int n_qubits, sv_dtype dtype, const sv_pauli* terms, int n_terms,
+                            double* d_out, void* hip_stream)
+{
+    g_err.clear();
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    if (n_qubits < 1 || n_qubits > kMaxQubits) return fail(SV_EINVAL, "n_qubits must be in [1, 34]");
+    if (!state || !d_out) return fail(SV_EINVAL, "null state or output");
+    if (reinterpret_cast<uintptr_t>(state) % 16) return fail(SV_EINVAL, "state not 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_out) % 8) return fail(SV_EINVAL, "output not 8-byte aligned");
+    if (n_terms < 0) return fail(SV_EINVAL, "n_terms < 0");
+    if (n_terms > 0 && !terms) return fail(SV_EINVAL, "null term array");
+    const uint64_t all = (1ull << n_qubits) - 1;
+    for (int t = 0; t < n_terms; t++) {
+        if ((terms[t].x_mask | terms[t].z_mask) & ~all) return fail(SV_EINVAL, "a term acts on a qubit >= n");
+        if (!std::isfinite(terms[t].coeff)) return fail(SV_EINVAL, "non-finite coefficient");
+    }
+    int nb = 0;
+    visit_batches(terms, n_terms, [&](const TermBatch&) { nb++; });
+    if (nb > kNoAllocMaxBatches)
+        return fail(SV_EINVAL, "more than 64 term batches (a batch is up to 16 terms sharing one x mask)");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    double* part = nullptr;
+    sv_status st = scratch_for_device(dev, &part);
+    if (st != SV_OK) return st;
+    double* rows = part + (size_t)kNoAllocMaxBatches * kReduceBlocks;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int np = kReduceBlocks;
+    // The launches and the order of the sums are those of sv_expect, so the
+    // two give the same double.
+    int k = 0;
+    hipError_t err = hipSuccess;
+    visit_batches(terms, n_terms, [&](const TermBatch& tb) {
+        if (err != hipSuccess) return;
+        err = dtype == SV_C128
+                  ? launch_pauli_expect<d2>(static_cast<const d2*>(state), n_qubits, tb, part + (size_t)k * np, np,
+                                            stream)
+                  : launch_pauli_expect<f2>(static_cast<const f2*>(state), n_qubits, tb, part + (size_t)k * np, np,
+                                            stream);
+        k++;
+    });
+    HIP_TRY(err);
+    HIP_TRY(launch_sum_rows(part, nb, np, np, rows, stream));
+    HIP_TRY(launch_sum_ordered(rows, nb, d_out, stream));
     return SV_OK;
 }
 

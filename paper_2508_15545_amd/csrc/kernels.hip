@@ -759,6 +759,23 @@ hipError_t launch_sum_rows(const double* partials, int rows, int64_t count, int6
     return hipGetLastError();
 }
 
+// out[0] = ((0 + rows[0]) + rows[1]) + ... + rows[count - 1]: one thread,
+// in index order (the same additions a host loop over the rows makes).
+__global__ __launch_bounds__(64) void k_sum_ordered(const double* __restrict__ rows, int count,
+                                                    double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double f = 0;
+    for (int k = 0; k < count; k++) f += rows[k];
+    out[0] = f;
+}
+
+hipError_t launch_sum_ordered(const double* rows, int count, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, rows, count, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_compare_finish(const double* partials, int n_part, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_sum_rows, dim3(6), dim3(kThreads), 0, st, partials, (int64_t)n_part, (int64_t)n_part, out,

@@ -330,6 +330,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 // out[r] = sum over c of partials[r * stride + c], c < count, fixed order.
 hipError_t launch_sum_rows(const double* partials, int rows, int64_t count, int64_t stride, double* out,
                            hipStream_t st);
+// out[0] = sum of rows[0..count) added one after another in index order.
+hipError_t launch_sum_ordered(const double* rows, int count, double* out, hipStream_t st);
 // Compare partial rows combine: max for row 0, sums for the rest (6 rows).
 hipError_t launch_compare_finish(const double* partials, int n_part, double* out, hipStream_t st);
 
