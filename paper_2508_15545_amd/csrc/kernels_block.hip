@@ -203,6 +203,22 @@ __device__ __forceinline__ void reg_dense1(T (&v)[NS][1 << RB], T u00, T u01, T 
     }
 }
 
+// x with the sign bits of both components XORed with m (0 or 0x80000000):
+// x or -x exactly.
+__device__ __forceinline__ d2 flip_sign(d2 x, uint32_t m)
+{
+    const uint64_t mm = (uint64_t)m << 32;
+    x.x = __longlong_as_double(__double_as_longlong(x.x) ^ (long long)mm);
+    x.y = __longlong_as_double(__double_as_longlong(x.y) ^ (long long)mm);
+    return x;
+}
+__device__ __forceinline__ f2 flip_sign(f2 x, uint32_t m)
+{
+    x.x = __int_as_float(__float_as_int(x.x) ^ (int)m);
+    x.y = __int_as_float(__float_as_int(x.y) ^ (int)m);
+    return x;
+}
+
 // Register permutations (X, CNOT, SWAP) multiply by `one` (always 1.0,
 // exact) so that they are computed into the registers they overwrite: a
 // plain move would be compiled as a renaming, and every path through the op
@@ -281,6 +297,49 @@ __device__ __forceinline__ void reg_dense2(T (&v)[NS][1 << RB], const T* __restr
     }
 }
 
+// The 4x4 update of reg_dense2 on the matrix cores (complex64, one state).
+// v_mfma_f32_4x4x1f32 treats the wave as 16 blocks of 4 lanes; in block b it
+// adds A[i] * B[j] to output register i of lane 4b + j, with A[i] taken from
+// lane 4b + i and B[j] from lane 4b + j. With B = element e of a lane's own
+// quadruple and A = column e of the matrix (lane 4b + i holding row i), one
+// instruction adds M[i][e] x_e to output i of every lane's quadruple, so the
+// quadruple stays in its lane's registers. Real and imaginary parts take
+// four such steps per e: yr += Mr x_r - Mi x_i, yi += Mi x_r + Mr x_i.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int RB, int J0, int J1>
+__device__ __forceinline__ void reg_dense2_mfma(f2 (&v)[1][1 << RB], const f2* __restrict__ m, int lane)
+{
+    const f2* row = m + 4 * (lane & 3);  // this lane's A operands: row (lane mod 4) of the matrix
+    float ar[4], ai[4], an[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const f2 u = row[e];
+        ar[e] = u.x;
+        ai[e] = u.y;
+        an[e] = -u.y;
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << RB); k++) {
+        if (k & ((1 << J0) | (1 << J1))) continue;
+        const int idx[4] = {k, k | (1 << J0), k | (1 << J1), k | (1 << J0) | (1 << J1)};
+        f32x4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const f2 x = v[0][idx[e]];
+            yr = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[e], x.x, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f32_4x4x1f32(ai[e], x.x, yi, 0, 0, 0);
+            yr = __builtin_amdgcn_mfma_f32_4x4x1f32(an[e], x.y, yr, 0, 0, 0);
+            yi = __builtin_amdgcn_mfma_f32_4x4x1f32(ar[e], x.y, yi, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            v[0][idx[i]].x = yr[i];
+            v[0][idx[i]].y = yi[i];
+        }
+    }
+}
+
 template <typename T, int RB, int NS, int J0, int J1, bool CTRL>
 __device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type one)
 {
@@ -337,16 +396,19 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double c
 // waves per SIMD, which its half-size exchange buffer lets the LDS hold; the
 // single-state complex64 one to 96 VGPRs, five waves per SIMD, as many as
 // its 32 KiB exchange buffers let a CU's LDS hold.
-template <typename T, int RB, int NS, bool PF>
+template <typename T, int RB, int NS, bool PF, bool MF = false>
 constexpr int block_waves_per_eu()
 {
-    return (RB == 3 && NS == 1) ? (PF ? 3 : 4)
+    return MF ? 4
+         : (RB == 3 && NS == 1) ? (PF ? 3 : 4)
          : (split_exchange<T, NS>() && !PF) ? 3
          : (sizeof(T) == 8 && NS == 1 && !PF) ? 5 : 1;
 }
 
-template <typename T, int RB, int NS, bool PF>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<T, RB, NS, PF>())))
+// MF: the variant whose plans may hold matrix-core 4x4 ops (RC_D2M); a kernel
+// of its own, so that their registers do not weigh on the default kernel.
+template <typename T, int RB, int NS, bool PF, bool MF>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<T, RB, NS, PF, MF>())))
 void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                                                    const PassHdr* __restrict__ hdr,
                                                    const StageHdr* __restrict__ stages,
@@ -496,6 +558,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #define F_D2(A, B) reg_dense2<T, RB, NS, A, B, false>(v, mats + cur.mat, cm)
 #define F_D2C(A, B) reg_dense2<T, RB, NS, A, B, true>(v, mats + cur.mat, cm)
 #define F_SW(A, B) reg_swap<T, RB, NS, A, B, false>(v, cm, one)
+#define F_D2M(A, B) if constexpr (MF && sizeof(T) == 8 && NS == 1) { reg_dense2_mfma<RB, A, B>(v, mats + cur.mat, lane); }
 #define F_SWC(A, B) reg_swap<T, RB, NS, A, B, true>(v, cm, one)
                 QV_ALL1(RC_D1, F_D1)
                 QV_ALL1(RC_D1C, F_D1C)
@@ -504,6 +567,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 QV_ORDERED(RC_CX, F_CX)
                 QV_PAIRS(RC_D2, F_D2)
                 QV_PAIRS(RC_D2C, F_D2C)
+                QV_PAIRS(RC_D2M, F_D2M)
                 QV_PAIRS(RC_SW, F_SW)
                 QV_PAIRS(RC_SWC, F_SWC)
             case RC_DIAG: {
@@ -527,6 +591,21 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                         const T x = v[s][k];
                         const T y = cmul(d, x);
                         v[s][k] = on ? y : x;
+                    }
+                }
+                break;
+            }
+            case RC_SIGN: {
+                // flip the sign of the registers the op acts on: the thread's
+                // part of the condition is one sign mask, the register part
+                // (kmask) is uniform, so each register is a uniform test and
+                // two exclusive ors per component pair
+                const uint32_t tsign = (cur_tl & cur.tctrl) == cur.tctrl ? 0x80000000u : 0u;
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    if (cur.kmask & (1u << k)) {
+#pragma unroll
+                        for (int s = 0; s < NS; s++) v[s][k] = flip_sign(v[s][k], tsign);
                     }
                 }
                 break;
@@ -666,6 +745,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #undef F_D2C
 #undef F_SW
 #undef F_SWC
+#undef F_D2M
 #undef QV_M2
 #undef QV_ORDERED
 #undef QV_PAIRS
@@ -737,6 +817,14 @@ static bool prefetch_on()
     return v == 1;
 }
 
+// Matrix-core 4x4 updates for complex64 (QVEC_MFMA=1; the planner emits
+// RC_D2M ops only then, and those passes run the MF kernel).
+static bool mfma_on()
+{
+    const char* e = std::getenv("QVEC_MFMA");
+    return e && e[0] == '1' && e[1] == 0;
+}
+
 static int cu_count()
 {
     static int cus = 0;
@@ -744,12 +832,12 @@ static int cu_count()
     return cus;
 }
 
-template <typename T, int RB, int NS, bool PF>
+template <typename T, int RB, int NS, bool PF, bool MF = false>
 static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const StageHdr* d_stages,
                                const TileOp* d_ops, const T* d_mats, const PhaseTerm* d_phase, int b, double* gp,
                                int64_t gs, hipStream_t st)
 {
-    const void* fn = reinterpret_cast<const void*>(&k_block_reg<T, RB, NS, PF>);
+    const void* fn = reinterpret_cast<const void*>(&k_block_reg<T, RB, NS, PF, MF>);
     // the exchange buffer is a static array of the kernel
     if ((size_t)NS * ((size_t)1 << b) * xch_slot_bytes<T, NS>() > (size_t)NS * kRegLdsBytesPerState)
         return hipErrorInvalidValue;
@@ -774,8 +862,8 @@ static hipError_t launch_reg_k(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
         const uint64_t g = (uint64_t)per_cu * (uint64_t)cu_count();
         if (g < grid) grid = g;
     }
-    hipLaunchKernelGGL((k_block_reg<T, RB, NS, PF>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1, d_hdr,
-                       d_stages, d_ops, d_mats, d_phase, gp, gs);
+    hipLaunchKernelGGL((k_block_reg<T, RB, NS, PF, MF>), dim3((unsigned)grid), dim3(threads), lds, st, s0, s1,
+                       d_hdr, d_stages, d_ops, d_mats, d_phase, gp, gs);
     return hipGetLastError();
 }
 
@@ -787,6 +875,11 @@ static hipError_t launch_reg_t(T* s0, T* s1, int n, const PassHdr* d_hdr, const 
     if constexpr (NS == 1) {
         if (prefetch_on<T>())
             return launch_reg_k<T, RB, NS, true>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
+        if constexpr (sizeof(T) == 8 && RB == 4) {
+            if (mfma_on())
+                return launch_reg_k<T, RB, NS, false, true>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp,
+                                                            gs, st);
+        }
     }
     return launch_reg_k<T, RB, NS, false>(s0, s1, n, d_hdr, d_stages, d_ops, d_mats, d_phase, b, gp, gs, st);
 }

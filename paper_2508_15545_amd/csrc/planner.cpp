@@ -399,7 +399,7 @@ void set_io_offsets(PassHdr& h, int r, const int32_t* store_q)
 
 // Flat dispatch code of an op for the register kernel (after stages and
 // diagonal merging).
-int32_t reg_code(const TileOp& t)
+int32_t reg_code(const TileOp& t, bool mfma)
 {
     const bool ctrl = t.lctrl != 0;
     switch (t.kind) {
@@ -407,20 +407,46 @@ int32_t reg_code(const TileOp& t)
     case T_XPERM:
         if (t.j1 >= 0 && t.c >= 0 && t.lctrl == (1u << t.c)) return RC_CX + 5 * t.j0 + t.j1;
         return (ctrl ? RC_XC : RC_X) + t.j0;
-    case T_DENSE2: return (ctrl ? RC_D2C : RC_D2) + 5 * t.j0 + t.j1;
+    case T_DENSE2: return (ctrl ? RC_D2C : (mfma ? RC_D2M : RC_D2)) + 5 * t.j0 + t.j1;
     case T_SWAP: return (ctrl ? RC_SWC : RC_SW) + 5 * t.j0 + t.j1;
     case T_DIAG: return RC_DIAG;
     case T_PHASE: return RC_PHASE;
     case T_GRAD: return t.gen == GEN_Z ? RC_GZ : RC_GXY + t.j0;
     case T_GRADZ: return RC_GZM;
+    case T_SIGN: return RC_SIGN;
     default: return RC_NONE;
     }
 }
 
-void set_reg_codes(PlanPass& pp, int r)
+// A diagonal whose entries are all 1 except a -1 on the all-ones corner (CZ,
+// Z, and their controlled forms) multiplies the amplitudes whose bits at its
+// qubits (and controls) are all 1 by -1: a sign flip of those amplitudes,
+// with the qubits joining the controls. The register kernel selects them as
+// it selects the registers of a controlled op and flips their sign bits,
+// which is exact, instead of a complex product per amplitude.
+void diag_to_sign(PlanPass& pp)
 {
     for (TileOp& t : pp.ops) {
-        t.code = reg_code(t);
+        if (t.kind != T_DIAG) continue;
+        const cd* d = &pp.mats[t.mat];
+        const bool one_q = t.c < 0 && t.oc < 0;
+        const bool sign = one_q ? (d[0] == 1.0 && d[1] == -1.0)
+                                : (d[0] == 1.0 && d[1] == 1.0 && d[2] == 1.0 && d[3] == -1.0);
+        if (!sign) continue;
+        if (t.a >= 0) t.lctrl |= 1u << t.a;
+        else if (t.oa >= 0) t.gctrl |= 1ull << t.oa;
+        if (t.c >= 0) t.lctrl |= 1u << t.c;
+        else if (t.oc >= 0) t.gctrl |= 1ull << t.oc;
+        t.kind = T_SIGN;
+        t.a = t.c = t.oa = t.oc = -1;
+        t.j0 = t.j1 = -1;
+    }
+}
+
+void set_reg_codes(PlanPass& pp, int r, bool mfma)
+{
+    for (TileOp& t : pp.ops) {
+        t.code = reg_code(t, mfma);
         t.tctrl = 0;
         t.kmask = (1u << r) - 1;
     }
@@ -1403,7 +1429,8 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             pp.reg_bits = opt.reg_bits;
             if (opt.merge_diagonals) merge_diagonals(pp, opt.reg_bits);
             if (opt.group_reads && grads > 1) group_z_reads(pp, opt.reg_bits);
-            set_reg_codes(pp, opt.reg_bits);
+            diag_to_sign(pp);
+            set_reg_codes(pp, opt.reg_bits, opt.mfma && elem == 8 && opt.n_states == 1);
             set_io_offsets(pp.hdr, opt.reg_bits, moved ? store_q : nullptr);
             check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);
         }
@@ -1480,7 +1507,8 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         plan_stages(pp, b, opt.reg_bits, opt.wave_mode, elem, opt.lds_elem > 0 ? opt.lds_elem : elem, store_first,
                     moved_mask);
         pp.reg_bits = opt.reg_bits;
-        set_reg_codes(pp, opt.reg_bits);
+        diag_to_sign(pp);
+        set_reg_codes(pp, opt.reg_bits, opt.mfma && elem == 8 && opt.n_states == 1);
         set_io_offsets(pp.hdr, opt.reg_bits, store_q);
         check_mappings(pp, opt.reg_bits, store_q);
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;

@@ -63,6 +63,9 @@ enum TileKind : int32_t {
                    // terms phase[mat .. mat + cnt) (register kernel only)
     T_GRADZ = 7,   // several Z reads in one pass over the registers: ReadZ
                    // records phase[aux .. aux + cnt) (register kernel only)
+    T_SIGN = 8,    // negate the amplitudes whose local bits cover lctrl (the
+                   // block base covering gctrl): CZ, Z and controlled Z
+                   // (register kernel only)
 };
 
 struct TileOp {
@@ -105,6 +108,9 @@ enum RegCode : int32_t {
     RC_GZ = 194,    // gradient read, G = Z
     RC_GZM = 195,   // several gradient reads with G = Z (T_GRADZ)
     RC_GXY = 200,   // + j0: gradient read, G = X or Y on window bit j0
+    RC_D2M = 224,   // + 5 j0 + j1: dense 4x4 on window bits j0 < j1 on the matrix
+                    // cores (complex64 single-state kernel only)
+    RC_SIGN = 248,  // sign flip of the registers the op acts on (T_SIGN)
 };
 
 // Terms of a phase polynomial, angles in turns (1 = 2 pi). The phase of an
@@ -252,6 +258,8 @@ struct PlanOptions {
     bool park = false;            // move qubits between passes: each pass's store may permute its
                                   // local qubits (single-state register passes only)
     bool group_reads = true;      // Z reads waiting together share one op (register kernel)
+    bool mfma = false;            // uncontrolled 4x4 updates as matrix-core ops (RC_D2M; complex64,
+                                  // single state)
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its

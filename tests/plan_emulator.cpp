@@ -116,6 +116,9 @@ static void run_block_pass(std::vector<C>& psi, int n, const PlanPass& pp)
                         const int bc = t.c >= 0 ? bit(l, t.c) : (t.oc >= 0 ? bit(base, t.oc) : 0);
                         blk[l] *= M[ba + 2 * bc];
                     }
+                } else if (t.kind == T_SIGN) {
+                    for (uint32_t l = 0; l < L; l++)
+                        if ((l & t.lctrl) == t.lctrl) blk[l] = -blk[l];
                 } else if (t.kind == T_PHASE) {
                     const PhaseHead& ph = *reinterpret_cast<const PhaseHead*>(&pp.phase[t.aux]);
                     for (uint32_t tid = 0; tid < (1u << tb); tid++) {

@@ -488,3 +488,28 @@ def test_autograd_function_complex64(qv):
     f_o, g_o = oracle.adjoint_grad(circ, n, H, th.numel())
     assert abs(f.item() - f_o) <= 1e-5
     assert np.max(np.abs(th.grad.numpy() - 2.0 * g_o)) <= 1e-4
+
+
+# ------------------------------------------------------------ matrix cores ---
+
+@pytest.mark.parametrize("kind,n,seed", [("mixed", 13, 0), ("mixed", 16, 1), ("cx", 19, 2), ("cz", 22, 3),
+                                         ("qft", 17, 4)])
+def test_complex64_matrix_core_4x4(qv, monkeypatch, kind, n, seed):
+    """complex64 with the 4x4 updates on the matrix cores (QVEC_MFMA=1)
+    against the oracle, and against the default path."""
+    print(f"mfma {kind} n={n} seed={seed}", flush=True)
+    if kind == "qft":
+        circ = C.qft(n)
+    elif kind == "mixed":
+        circ = C.random_mixed_circuit(n, 300, seed)
+    else:
+        circ = C.random_u3_layers(n, 12, seed, entangler=kind)
+    x = C.random_basis_index(n, seed)
+    want = oracle.run(circ, n, x0=x)
+    got = {}
+    for knob in ("1", "0"):
+        monkeypatch.setenv("QVEC_MFMA", knob)
+        st = qv.State(n, torch.complex64).set_basis(x).apply(circ)
+        got[knob] = host(st)
+        assert maxabs(got[knob], want) <= 1e-5, knob
+    assert maxabs(got["1"], got["0"]) <= 1e-5

@@ -40,8 +40,11 @@ def gate_lines(circ):
 
 CASES = [
     ("cx", 17, 8, 0), ("cx", 18, 10, 1), ("cx", 20, 10, 0), ("cx", 20, 10, 1), ("cx", 20, 10, 2),
-    ("cz", 19, 8, 3), ("qft", 16, 0, 0), ("qft", 19, 0, 0), ("hea", 15, 4, 0),
+    ("cz", 19, 8, 3), ("qft", 16, 0, 0), ("qft", 19, 0, 0), ("hea", 15, 4, 0), ("mixed", 16, 400, 5),
 ]
+# every op the gate-line format carries (no matrix gates): Z, CZ and the
+# other diagonals among dense gates on random qubits
+MIXED_OPS = tuple(op for op in C.ONE_QUBIT + C.TWO_QUBIT if op not in ("mat1", "mat2"))
 
 
 @pytest.mark.parametrize("park", [0, 1])
@@ -52,6 +55,8 @@ def test_planned_passes_equal_gate_by_gate(emulator, kind, n, depth, seed, elem,
         circ = C.qft(n)
     elif kind == "hea":
         circ = C.hea(n, depth, C.hea_params(n, depth, seed))
+    elif kind == "mixed":
+        circ = C.random_mixed_circuit(n, depth, seed, ops=MIXED_OPS)
     else:
         circ = C.random_u3_layers(n, depth, seed, entangler=kind)
     r = subprocess.run([emulator, str(n), str(elem), str(park)], input=gate_lines(circ), capture_output=True,
