@@ -94,31 +94,56 @@ def run_step(st, rand, x, qft):
     return n1, n2
 
 
-def cpu_baseline(n: int, rand, seconds_budget: float = 20.0):
-    """The FP64 oracle on the first layers of the random circuit (the same
-    gates, the same 2^n-amplitude state), timed around the gate loop only,
-    stopping after the gate that crosses the time budget."""
-    import oracle
+def host_cpus() -> int:
+    """CPUs this process may run on (what nproc reports)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
-    per_layer = n + n // 2
-    sample = rand[: 4 * per_layer]
-    s = oracle.basis_state(n, 0)
+
+def _oracle_rate(oracle, n, s, gates, budget):
+    """Apply gates one by one to s until the time budget is crossed; return
+    (gates done, seconds) around the gate loop only."""
     t0 = time.perf_counter()
     done = 0
-    for g in sample:
+    for g in gates:
         oracle.apply_gate(s, n, g)
         done += 1
-        if time.perf_counter() - t0 > seconds_budget:
+        if time.perf_counter() - t0 > budget:
             break
-    dt = time.perf_counter() - t0
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(n: int, rand, x, qft, budget: float = 8.0):
+    """The FP64 oracle on bounded samples of the same workload (the same
+    gates on the same 2^n-amplitude state), timed around the gate loop only:
+    the random circuit from |0..0> and the QFT from the seeded basis state on
+    all the oracle's threads, then the random circuit again on one thread.
+    Each leg stops after the gate that crosses its time budget."""
+    import oracle
+
+    threads = oracle.num_threads()
+    s = oracle.basis_state(n, 0)
+    d_r, t_r = _oracle_rate(oracle, n, s, rand, budget)
+    s = oracle.basis_state(n, x)
+    d_q, t_q = _oracle_rate(oracle, n, s, qft, budget / 2)
+    oracle.set_threads(1)
+    s = oracle.basis_state(n, 0)
+    d_1, t_1 = _oracle_rate(oracle, n, s, rand, budget)
+    oracle.set_threads(threads)
     del s
     return {
-        "value": done / dt,
+        "value": (d_r + d_q) / (t_r + t_q),
         "unit": "gate-applications/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {done} gates (U3 on every qubit + CNOT matching, layer by layer) of the {n}-qubit "
-                  f"random circuit on a complex128 state, {dt:.1f} s",
+        "sample": f"{n}-qubit complex128 state: first {d_r} gates of the random U3 + CNOT circuit ({t_r:.1f} s) "
+                  f"and first {d_q} gates of the QFT ({t_q:.1f} s) on {threads} threads; "
+                  f"first {d_1} gates of the random circuit on 1 thread ({t_1:.1f} s)",
+        "value_1_thread": d_1 / t_1,
+        "host_cpus": host_cpus(),
+        "host_mem_gib": round(os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 2 ** 30, 1),
     }
 
 
@@ -179,12 +204,50 @@ def timed(fn, reps=1):
     return (time.perf_counter() - t0) / reps, r
 
 
+def pcie_probe(gib: int = 2, reps: int = 3):
+    """Pinned host <-> device copy bandwidth (the host tier's roofline): one
+    direction at a time, then both at once on two streams, each copy a
+    single large transfer of `gib` GiB."""
+    n = gib << 27  # complex128 elements
+    h_in = torch.empty(n, dtype=torch.complex128, pin_memory=True)
+    h_out = torch.empty(n, dtype=torch.complex128, pin_memory=True)
+    d_in = torch.empty(n, dtype=torch.complex128, device="cuda")
+    d_out = torch.empty(n, dtype=torch.complex128, device="cuda")
+    h_in.zero_()
+    d_out.zero_()
+    nbytes = n * 16
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def run(h2d, d2h):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if h2d:
+                with torch.cuda.stream(s1):
+                    d_in.copy_(h_in, non_blocking=True)
+            if d2h:
+                with torch.cuda.stream(s2):
+                    h_out.copy_(d_out, non_blocking=True)
+        torch.cuda.synchronize()
+        return (h2d + d2h) * nbytes * reps / (time.perf_counter() - t0) / 1e9
+
+    run(True, True)
+    out = {"h2d_gbs": run(True, False), "d2h_gbs": run(False, True), "both_gbs": run(True, True),
+           "bytes_per_copy": nbytes}
+    del h_in, h_out, d_in, d_out
+    torch.cuda.empty_cache()
+    torch._C._host_emptyCache()
+    return out
+
+
 def host_tier(qv, n=30, chunk=28, depth=4):
     """Out-of-core tier: the random U3 + CNOT circuit on a complex128 state in
     pinned host memory, chunks of 2^chunk amplitudes through the GPU. The
     state is allocated and set outside the timed call; the call's own clock
-    covers the copies in and out and the device passes."""
+    covers the copies in and out and the device passes. The pinned-copy
+    probe beside it is the PCIe roofline of the tier."""
     import gc
+    probe = pcie_probe()
     st = torch.zeros(1 << n, dtype=torch.complex128, pin_memory=True)
     st[0] = 1
     circ = C.random_u3_layers(n, depth, 0)
@@ -193,11 +256,16 @@ def host_tier(qv, n=30, chunk=28, depth=4):
     norm = sum(float(torch.sum(st[i:i + step].abs() ** 2)) for i in range(0, 1 << n, step))
     del st
     gc.collect()
+    # hand the pinned block back while the HIP runtime is up, rather than
+    # from the host allocator's cache at interpreter exit
+    torch._C._host_emptyCache()
     moved = s["bytes_h2d"] + s["bytes_d2h"]
+    gbs = moved / s["seconds"] / 1e9
     return {"n_qubits": n, "dtype": "complex128", "state_gib": (1 << n) * 16 / 2 ** 30, "gates": len(circ),
             "depth": depth, "chunk_qubits": s["chunk_qubits"], "high_qubits": s["high_qubits"],
             "chunks_per_pass": s["n_chunks"], "passes": s["n_passes"], "seconds": s["seconds"],
-            "gate_app_per_s": len(circ) / s["seconds"], "pcie_gbs_both_directions": moved / s["seconds"] / 1e9,
+            "gate_app_per_s": len(circ) / s["seconds"], "pcie_gbs_both_directions": gbs,
+            "pcie_probe": probe, "frac_of_probe_both": gbs / probe["both_gbs"],
             "norm_error": abs(norm - 1)}
 
 
@@ -269,6 +337,33 @@ def adjoint_figures(qv, n=24, layers=20, dtype=torch.complex64, shift_evals=True
     return out
 
 
+def mfma_probe(qv, B, n, steps):
+    """complex64 benchmark step with the 4x4 updates on the VALU (default)
+    and on the matrix cores (QVEC_MFMA=1): block-pass launch time and the
+    device-side difference of the two final states."""
+    rand, x, qft = workload(n)
+    out = {}
+    states = {}
+    for knob in ("0", "1", "0"):
+        os.environ["QVEC_MFMA"] = knob
+        st = qv.State(n, torch.complex64)
+        run_step(st, rand, x, qft)
+        st.timing(True)
+        st.timing_reset()
+        for _ in range(steps):
+            run_step(st, rand, x, qft)
+        launches, ms = st.timing_read(B.KF_BLOCK)
+        st.timing(False)
+        st.set_basis(0).apply(rand)
+        states[knob] = st
+        out[f"mfma{knob}_block_ms_per_launch"] = ms / launches
+        out[f"mfma{knob}_block_ms_per_step"] = ms / steps
+    os.environ.pop("QVEC_MFMA", None)
+    d = states["0"].compare(states["1"])
+    out["max_abs_diff_random_circuit"] = d["max_abs"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +379,10 @@ def main() -> int:
                     help="only time one unfused U3 sweep per target qubit (the one-qubit sweep kernel)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only the 24-qubit ansatz forward and adjoint figures (no parameter shift)")
+    ap.add_argument("--c64-vs-c128", action="store_true",
+                    help="only the 33-qubit random U3 + CZ circuit in complex128 and complex64")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only the block-pass time of the step in complex64 with and without matrix-core 4x4 updates")
     ap.add_argument("--host-tier", action="store_true",
                     help="only the host tier on a 30-qubit complex128 state in pinned host memory")
     args = ap.parse_args()
@@ -310,6 +409,12 @@ def main() -> int:
     if args.host_tier:
         print(json.dumps({"host_tier": host_tier(qv)}), flush=True)
         return 0
+    if args.c64_vs_c128:
+        print(json.dumps({"c64_vs_c128": c64_vs_c128(qv)}), flush=True)
+        return 0
+    if args.mfma_probe:
+        print(json.dumps({"mfma_probe": mfma_probe(qv, B, n, args.steps)}), flush=True)
+        return 0
     rand, x, qft = workload(n)
     gates_per_step = len(rand) + len(qft)
     plan_r = qv.plan_stats(n, dtype, rand)
@@ -323,8 +428,7 @@ def main() -> int:
         run_step(st, rand, x, qft)
         log(f"warmup {w + 1}/{args.warmup} done")
 
-    st.timing(True)
-    st.timing_reset()
+    # The headline: the steps alone, no per-launch instrumentation.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     norms = []
@@ -333,7 +437,19 @@ def main() -> int:
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    # The same steps again with HIP events around every launch on the launch
+    # stream: per-kernel launch counts and durations for the roofline.
+    st.timing(True)
+    st.timing_reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        run_step(st, rand, x, qft)
+    torch.cuda.synchronize()
+    elapsed_instr = time.perf_counter() - t1
     st.timing(False)
+    log(f"instrumented repeat of {args.steps} steps done")
 
     fams = {"block": B.KF_BLOCK, "sweep1": B.KF_SWEEP1, "sweep2": B.KF_SWEEP2, "diag": B.KF_DIAG,
             "reduce": B.KF_REDUCE, "init": B.KF_INIT}
@@ -358,6 +474,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_instrumented": elapsed_instr / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -408,7 +525,7 @@ def main() -> int:
         out["host_tier"] = host_tier(qv)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(n, rand)
+        out["cpu_baseline"] = cpu_baseline(n, rand, x, qft)
     print(json.dumps(out), flush=True)
     return 0
 

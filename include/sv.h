@@ -158,7 +158,8 @@ void* sv_data(sv_state s);
 int sv_num_qubits(sv_state s);
 sv_dtype sv_get_dtype(sv_state s);
 
-/* psi = e_x (amplitude x set to 1, all others 0): one write pass.
+/* Set the amplitude vector of Sec. II Eq. 1 to the basis state e_x:
+ * alpha_x = 1, every other alpha_i = 0. One write pass over the state.
  * Errors: SV_EINVAL if x >= 2^n. */
 sv_status sv_set_basis(sv_state s, uint64_t x);
 
@@ -197,7 +198,7 @@ sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gate
  * each shared qubit both act diagonally), so the result equals applying the
  * gates in order; each chunk of a pass goes host -> device,
  * through the fused device path (as sv_apply_fused on a c-qubit state) and
- * back. Two device buffers of 2^c * S_state bytes are allocated for the call
+ * back. Three device buffers of 2^c * S_state bytes are allocated for the call
  * and freed before it returns; copies in, passes and copies out of three
  * chunks overlap on three streams of the current device. Synchronous: the
  * host state holds the result on return. stats may be NULL.
@@ -207,11 +208,17 @@ sv_status sv_plan(int n_qubits, sv_dtype dtype, const sv_gate* gates, int n_gate
 sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv_gate* gates,
                         int n_gates, int chunk_qubits, sv_host_stats* stats);
 
-/* out = <psi|psi>, accumulated in double. Waits for the stream. */
+/* The calls from here to sv_adjoint_grad are additions of this engine, not
+ * part of the paper's method (which only applies gates): FP64 reductions
+ * over the state and the adjoint gradient of an expectation value.
+ *
+ * out = <psi|psi> = sum_i |alpha_i|^2 over the amplitudes of Sec. II Eq. 1
+ * (1 for a normalized state), accumulated in double. Waits for the stream. */
 sv_status sv_norm2(sv_state s, double* out);
 
-/* out = <psi|H|psi> for H = sum_t terms[t].coeff * P_t, accumulated in
- * double with a fixed-shape (deterministic) reduction. Waits for the stream.
+/* out = <psi|H|psi> for H = sum_t terms[t].coeff * P_t (an addition: the
+ * paper defines no observable), accumulated in double with a fixed-shape
+ * (deterministic) reduction. Waits for the stream.
  * Errors: SV_EINVAL if a mask has bits >= n. */
 sv_status sv_expect(sv_state s, const sv_pauli* terms, int n_terms, double* out);
 
@@ -236,12 +243,15 @@ sv_status sv_expect(sv_state s, const sv_pauli* terms, int n_terms, double* out)
 sv_status sv_expect_noalloc(const void* state, int n_qubits, sv_dtype dtype, const sv_pauli* terms,
                             int n_terms, double* d_out, void* hip_stream);
 
-/* dst = H psi (same dtype and size as s; dst_buf is caller device memory of
- * >= 2^n * S_state bytes, not overlapping the state). Enqueue only. */
+/* dst = H psi (an addition: the seed of the adjoint sweep; same dtype and
+ * size as s; dst_buf is caller device memory of >= 2^n * S_state bytes, 16-byte
+ * aligned, not overlapping the state). Enqueue only. */
 sv_status sv_apply_pauli_sum(sv_state s, const sv_pauli* terms, int n_terms, void* dst_buf,
                              size_t dst_bytes);
 
-/* Adjoint gradient of f(theta) = <psi|H|psi> with psi = U_L .. U_1 psi_0.
+/* Adjoint gradient of f(theta) = <psi|H|psi> with psi = U_L .. U_1 psi_0 (an
+ * addition: the paper has no parameterized circuits; the reverse sweep
+ * applies each inverse gate by the same pair updates, Sec. III.A Eq. 5).
  * On entry s holds psi = U_L .. U_1 psi_0 (the caller ran the circuit);
  * on return it holds the state recomputed back to psi_0 by applying the
  * inverse gates (no checkpoints). work_buf (>= 2^n * S_state bytes, device,

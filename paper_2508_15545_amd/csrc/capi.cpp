@@ -551,7 +551,7 @@ sv_status pauli_apply_impl(sv_state s, const T* psi, T* dst, const std::vector<T
 // amplitudes) and h high qubits chosen per pass, so one chunk is 2^h runs.
 // A pass takes the gates whose qubits (targets and controls) fit in its
 // chunk and that commute with the gates it leaves for later; each chunk is
-// then a c-qubit state for the device planner. Two device buffers and three streams overlap the copy-in of one
+// then a c-qubit state for the device planner. Three device buffers and three streams overlap the copy-in of one
 // chunk, the passes over another and the copy-out of a third.
 namespace {
 
@@ -851,17 +851,21 @@ sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv
     if (hp.empty()) return SV_OK;
     const auto t0 = std::chrono::steady_clock::now();
 
+    // Three device buffers in rotation: the copy-in of chunk k + 1 waits only
+    // for the copy-out of chunk k - 2, so copies in and out overlap while
+    // chunk k is on the device.
+    constexpr int NB = 3;
     hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
-    void* dbuf[2] = {nullptr, nullptr};
-    sv_state hs[2] = {nullptr, nullptr};
-    hipEvent_t ev[7] = {};  // in_done[2], comp_done[2], out_done[2], pass_done
-    hipEvent_t *in_done = ev, *comp_done = ev + 2, *out_done = ev + 4, &pass_done = ev[6];
+    void* dbuf[NB] = {};
+    sv_state hs[NB] = {};
+    hipEvent_t ev[3 * NB + 1] = {};  // in_done[NB], comp_done[NB], out_done[NB], pass_done
+    hipEvent_t *in_done = ev, *comp_done = ev + NB, *out_done = ev + 2 * NB, &pass_done = ev[3 * NB];
     auto body = [&]() -> sv_status {
         HIP_TRY(hipStreamCreate(&s_in));
         HIP_TRY(hipStreamCreate(&s_comp));
         HIP_TRY(hipStreamCreate(&s_out));
         for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        for (int b = 0; b < 2; b++) {
+        for (int b = 0; b < NB; b++) {
             if (hipMalloc(&dbuf[b], chunk_bytes) != hipSuccess) {
                 (void)hipGetLastError();
                 dbuf[b] = nullptr;
@@ -870,7 +874,7 @@ sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv
             sv_status a = sv_alloc(&hs[b], c, dtype, dbuf[b], chunk_bytes, s_comp);
             if (a != SV_OK) return a;
         }
-        bool used[2] = {false, false}, have_pass = false;
+        bool used[NB] = {}, have_pass = false;
         for (const HostPass& p : hp) {
             std::vector<HostGate> cg;
             sv_status bs = build_gates(hs[0], p.gates.data(), (int)p.gates.size(), &cg);
@@ -887,7 +891,7 @@ sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv
             for (int q = 0; q < n; q++)
                 if (!(local >> q & 1)) outer[n_outer++] = q;
             for (uint64_t k = 0; k < n_chunks; k++) {
-                const int b = (int)(k & 1);
+                const int b = (int)(k % NB);
                 uint64_t base = 0;
                 for (int i = 0; i < n_outer; i++) base |= ((k >> i) & 1ull) << outer[i];
                 if (used[b]) HIP_TRY(hipStreamWaitEvent(s_in, out_done[b], 0));
@@ -930,7 +934,7 @@ sv_status sv_host_apply(void* host_state, int n_qubits, sv_dtype dtype, const sv
     // release in dependency order; a failure above still drains the streams
     for (hipStream_t q : {s_in, s_comp, s_out})
         if (q && hipStreamSynchronize(q) != hipSuccess && res == SV_OK) res = fail(SV_EDEVICE, "host tier stream failed");
-    for (int b = 0; b < 2; b++) {
+    for (int b = 0; b < NB; b++) {
         if (hs[b]) (void)sv_free(hs[b]);
         if (dbuf[b]) (void)hipFree(dbuf[b]);
     }
