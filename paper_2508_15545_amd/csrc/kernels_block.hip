@@ -363,22 +363,27 @@ __device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typen
 }
 
 // Im <lambda|G|phi> contributions of the thread's registers for
-// G = cx X + cy Y on window bit J (v[0] = phi, v[1] = lambda).
+// G = cx X + cy Y on window bit J (v[0] = phi, v[1] = lambda). The per-thread
+// partial is formed in the state's precision (FP32 for complex64: the
+// thread's 2^RB products per component, summed in registers) and handed to
+// the FP64 reductions across lanes, waves and blocks.
 template <typename T, int RB, int J>
 __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double cx, double cy)
 {
-    double acc = 0;
+    using R = typename RealOf<T>::type;
+    R sx = 0, sy = 0;
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
         const int p = k ^ (1 << J);
         const T f = v[0][p], m = v[1][k];
-        const double re = (double)m.x * (double)f.x + (double)m.y * (double)f.y;
-        const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+        const R re = m.x * f.x + m.y * f.y;
+        const R im = m.x * f.y - m.y * f.x;
         const bool bit = (k >> J) & 1;
         // X: Im(conj(m) f); Y: (Y phi)_l = (bit ? i : -i) phi_{l ^ J}
-        acc += cx * im + cy * (bit ? re : -re);
+        sx += im;
+        sy += bit ? re : -re;
     }
-    return acc;
+    return cx * (double)sx + cy * (double)sy;
 }
 
 #define QV_J1_CASES(F)                                   \
@@ -675,7 +680,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
             }
             case RC_GZ: {
                 if constexpr (NS == 2) {
-                    double acc = 0;
+                    // per-thread partial in the state's precision, FP64 beyond
+                    typename RealOf<T>::type pacc = 0;
                     const int a = op.a;
                     const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
                     uint32_t tlx = cur_tl;
@@ -685,10 +691,10 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                         const uint32_t l = tlx | window_part<RB>(k, cur_w);
                         const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
                         const T f = v[0][k], m = v[1][k];
-                        const double im = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
-                        acc += bit ? -im : im;
+                        const auto im = m.x * f.y - m.y * f.x;
+                        pacc += bit ? -im : im;
                     }
-                    acc = wave_total(acc);
+                    const double acc = wave_total((double)pacc);
                     if (lane == 0) red[op.slot * 8 + wave] = acc;
                 }
                 break;
@@ -698,13 +704,15 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 // read of window bit j is sum_k (-1)^(k_j) p_k and a read of a
                 // thread bit or an outer qubit is +-sum_k p_k
                 if constexpr (NS == 2) {
-                    double S = 0, D[RB];
+                    // per-thread sums in the state's precision, FP64 beyond
+                    using RT = typename RealOf<T>::type;
+                    RT S = 0, D[RB];
 #pragma unroll
                     for (int j = 0; j < RB; j++) D[j] = 0;
 #pragma unroll
                     for (int k = 0; k < R; k++) {
                         const T f = v[0][k], m = v[1][k];
-                        const double p = (double)m.x * (double)f.y - (double)m.y * (double)f.x;
+                        const RT p = m.x * f.y - m.y * f.x;
                         S += p;
 #pragma unroll
                         for (int j = 0; j < RB; j++) D[j] += ((k >> j) & 1) ? -p : p;
@@ -713,16 +721,16 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                     const uint32_t utid = (uint32_t)tid;
                     for (int e = 0; e < op.cnt; e++) {
                         const int zj = rz[e].j, ztb = rz[e].tbit, zoa = rz[e].oa, zslot = rz[e].slot;
-                        double val;
+                        RT pv;
                         if (zj >= 0) {
-                            val = D[0];
+                            pv = D[0];
 #pragma unroll
-                            for (int j = 1; j < RB; j++) val = zj == j ? D[j] : val;
+                            for (int j = 1; j < RB; j++) pv = zj == j ? D[j] : pv;
                         } else {
                             const bool bit = ztb >= 0 ? ((utid >> ztb) & 1u) != 0 : ((base >> zoa) & 1ull) != 0;
-                            val = bit ? -S : S;
+                            pv = bit ? -S : S;
                         }
-                        val = wave_total(val);
+                        const double val = wave_total((double)pv);
                         if (lane == 0) red[zslot * 8 + wave] = val;
                     }
                 }
