@@ -6,23 +6,29 @@ Workload (one step): on a 29-qubit complex128 state (8 GiB in HBM)
       1720 gates), then the FP64 norm;
   (b) reset to a seeded random basis state, run the textbook QFT (449 gates),
       then the FP64 norm.
-value = gates applied per second over the timed steps (2169 gates per step).
-The dominant kernel's achieved bandwidth comes from HIP events around each
-of its launches (library timing on the launch stream); the CPU baseline is
-the FP64 oracle on a bounded sample of the same workload.
+value = gates applied per second over the timed steps (2169 gates per step),
+which run without per-launch instrumentation. The same steps are then run
+again with HIP events around every launch on the launch stream (library
+timing) for the dominant kernel's achieved bandwidth; the CPU baseline is
+the FP64 oracle on bounded samples of the same workload.
 
 Besides the headline value the line carries, measured in the same run:
-  sweeps       one-qubit sweep kernel bandwidth for every target qubit;
-  copy         the library's streaming copy kernel (bandwidth reference);
-  c64_vs_c128  33-qubit random U3 + CZ circuit, depth 30, in complex128 and
-               complex64 (speedup and the device-side difference);
-  adjoint      24-qubit hardware-efficient ansatz, 20 layers (960
-               parameters), complex64: forward, adjoint backward, their
-               ratio, 2 x 960 parameter-shift evaluations, gradient error
-               against the complex128 adjoint.
+  sweeps            one-qubit sweep kernel bandwidth for every target qubit;
+  two_qubit_sweeps  unfused CNOT / SWAP / CZ / CP / 4x4 sweeps on several
+                    qubit pairs, against each one's algorithmic bytes;
+  copy              the library's streaming copy kernel (bandwidth reference);
+  c64_vs_c128       33-qubit random U3 + CZ circuit, depth 30, in complex128
+                    and complex64 (speedup and the device-side difference);
+  adjoint           24-qubit hardware-efficient ansatz, 20 layers (960
+                    parameters), complex64: forward, adjoint backward, their
+                    ratio, 2 x 960 parameter-shift evaluations, gradient
+                    error against the complex128 adjoint;
+  host_tier         30-qubit complex128 state in pinned host memory through
+                    the GPU in chunks, beside a pinned-copy probe.
 
 Prints one JSON line. Flags: --gpus (only 1), --steps, --warmup, --n,
---dtype c128|c64, --no-cpu (skip the oracle leg), --no-extras.
+--dtype c128|c64, --no-cpu (skip the oracle leg), --no-extras, and the probe
+modes listed by --help.
 """
 from __future__ import annotations
 
@@ -193,6 +199,46 @@ def sweep_rates(qv, B, n, dtype, elem, reps):
     vals = list(out.values())
     return {"gbs_by_target": out, "min_gbs": min(vals), "mean_gbs": sum(vals) / len(vals),
             "frac_of_peak_min": min(vals) / HBM_PEAK_GBS, "frac_of_peak_mean": sum(vals) / len(vals) / HBM_PEAK_GBS}
+
+
+TWO_QUBIT_PAIRS = [(0, 1), (2, 11), (11, 20), (20, 28), (27, 5)]
+
+
+def two_qubit_sweep_rates(qv, B, n, dtype, elem, reps):
+    """Unfused two-qubit gates, one sweep kernel each: CNOT (the controlled
+    one-qubit sweep over the control-1 half), SWAP (the pairs whose two bits
+    differ), CZ and CP (the |11> quarter) and a general 4x4 (every
+    quadruple), for several qubit pairs. GB/s against the algorithmic bytes
+    of each: CNOT and SWAP 2^n S, CZ and CP 2^(n-1) S, 4x4 2 * 2^n S."""
+    torch.cuda.set_device(0)
+    st = qv.State(n, dtype, device="cuda:0").set_basis(0)
+    rng = C.rng_for(2)
+    S = (1 << n) * elem
+    kinds = {"cx": (B.KF_SWEEP1, S), "swap": (B.KF_SWEEP2, S), "cz": (B.KF_DIAG, S / 2),
+             "cp": (B.KF_DIAG, S / 2), "mat2": (B.KF_SWEEP2, 2 * S)}
+    out = {}
+    for kind, (fam, nbytes) in kinds.items():
+        rates = {}
+        for a, b in TWO_QUBIT_PAIRS:
+            if kind == "mat2":
+                g = C.gate("mat2", a, b, params=C.matrix_params(C.random_unitary(4, rng)))
+            elif kind == "cp":
+                g = C.gate("cp", a, b, params=(0.7,))
+            else:
+                g = C.gate(kind, a, b)
+            st.apply([g], fused=False)
+            st.timing(True)
+            st.timing_reset()
+            for _ in range(reps):
+                st.apply([g], fused=False)
+            launches, ms = st.timing_read(fam)
+            st.timing(False)
+            rates[f"{a},{b}"] = round(nbytes / (ms / launches / 1e3) / 1e9)
+        out[kind] = {"gbs_by_pair": rates, "min_gbs": min(rates.values()),
+                     "frac_of_peak_min": min(rates.values()) / HBM_PEAK_GBS}
+    del st
+    torch.cuda.empty_cache()
+    return out
 
 
 def timed(fn, reps=1):
@@ -377,6 +423,8 @@ def main() -> int:
                     help="only time the library's streaming copy kernel on two state-sized buffers")
     ap.add_argument("--sweeps", action="store_true",
                     help="only time one unfused U3 sweep per target qubit (the one-qubit sweep kernel)")
+    ap.add_argument("--two-qubit-sweeps", action="store_true",
+                    help="only time unfused CNOT / SWAP / CZ / CP / 4x4 sweeps on several qubit pairs")
     ap.add_argument("--adjoint", action="store_true",
                     help="only the 24-qubit ansatz forward and adjoint figures (no parameter shift)")
     ap.add_argument("--c64-vs-c128", action="store_true",
@@ -405,6 +453,10 @@ def main() -> int:
         return 0
     if args.adjoint:
         print(json.dumps({"adjoint": adjoint_figures(qv, shift_evals=False)}), flush=True)
+        return 0
+    if args.two_qubit_sweeps:
+        print(json.dumps({"two_qubit_sweeps": two_qubit_sweep_rates(qv, B, n, dtype, elem, args.steps)}),
+              flush=True)
         return 0
     if args.host_tier:
         print(json.dumps({"host_tier": host_tier(qv)}), flush=True)
@@ -514,6 +566,8 @@ def main() -> int:
         out["sweeps"] = {"min_gbs": sw["min_gbs"], "mean_gbs": sw["mean_gbs"],
                          "frac_of_peak_min": sw["frac_of_peak_min"], "frac_of_peak_mean": sw["frac_of_peak_mean"],
                          "gbs_by_target": {k: round(v) for k, v in sw["gbs_by_target"].items()}}
+        log("two-qubit sweeps ...")
+        out["two_qubit_sweeps"] = two_qubit_sweep_rates(qv, B, n, dtype, elem, 3)
         log("copy ...")
         out["copy"] = copy_rate(qv, B, n, dtype, elem, 5)
         out["sweeps"]["frac_of_copy_mean"] = sw["mean_gbs"] / out["copy"]["gbs"]

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <mutex>
@@ -531,9 +532,10 @@ sv_status pauli_apply_impl(sv_state s, const T* psi, T* dst, const std::vector<T
         HIP_TRY(launch_pauli_apply<T>(psi, dst, s->n, zero, false, s->stream));
         return SV_OK;
     }
-    for (size_t k = 0; k < batches.size(); k++) {
+    for (size_t k = 0; k < batches.size(); k += kBatchesPerLaunch) {
+        const int cnt = (int)std::min(batches.size() - k, (size_t)kBatchesPerLaunch);
         LaunchTimer tm(s, KF_REDUCE);
-        HIP_TRY(launch_pauli_apply<T>(psi, dst, s->n, batches[k], k > 0, s->stream));
+        HIP_TRY(launch_pauli_apply_multi<T>(psi, dst, s->n, batches.data() + k, cnt, k > 0, s->stream));
     }
     return SV_OK;
 }
@@ -1057,62 +1059,14 @@ sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const s
             return fail(SV_EINVAL, "gate " + std::to_string(i) + ": param_index >= n_params");
     DeviceGuard dg(s->device);
 
-    // Reverse sweep items: gradient read, then the inverse gate. A grad item's
-    // slot is its position among the grad items (reverse gate order).
-    std::vector<PlanItem> items;
-    std::vector<int> slot_gate;  // grad slot -> gate index
-    items.reserve(hg.size());
-    for (int l = n_gates - 1; l >= 0; l--) {
-        PlanItem it;
-        it.g = dagger(hg[l]);
-        it.g.gen = hg[l].gen;
-        if (hg[l].param >= 0) {
-            it.grad = true;
-            it.grad_slot = (int32_t)slot_gate.size();
-            slot_gate.push_back(l);
-        }
-        items.push_back(it);
-    }
-    fold_diagonals_into_reads(items);
-    std::vector<PlanPass> passes;
-    try {
-        PlanOptions o = plan_options(s->n, s->elem, 2);
-        o.single_gate_sweeps = false;
-        passes = plan_circuit(s->n, items, o, (int)s->elem);
-    } catch (const std::exception& e) {
-        return fail(SV_EINVAL, std::string("planner: ") + e.what());
-    }
-    // Renumber the grad reads pass by pass: the rows of one pass are
-    // contiguous in the device result array, in op order.
-    std::vector<int> rows_per_pass(passes.size(), 0);
-    std::vector<int> row_gate;  // result row -> gate index
-    for (size_t p = 0; p < passes.size(); p++) {
-        int local = 0;
-        for (TileOp& op : passes[p].ops) {
-            if (op.kind == T_GRAD) {
-                row_gate.push_back(slot_gate[op.slot]);
-                op.slot = local++;
-            } else if (op.kind == T_GRADZ) {
-                for (int e = 0; e < op.cnt; e++) {
-                    ReadZ z;
-                    std::memcpy(&z, &passes[p].phase[op.aux + e], sizeof(z));
-                    row_gate.push_back(slot_gate[z.slot]);
-                    z.slot = local++;
-                    std::memcpy(&passes[p].phase[op.aux + e], &z, sizeof(z));
-                }
-            }
-        }
-        rows_per_pass[p] = local;
-    }
-    const int n_grad = (int)row_gate.size();
-
     return dispatch(s, [&](auto* psi) -> sv_status {
         using T = std::remove_pointer_t<decltype(psi)>;
         T* lam = static_cast<T*>(work_buf);
+        // lambda = H psi and f = <psi|lambda> go to the device first; the
+        // reverse sweep is planned on the host while they run.
         const auto batches = batch_terms(terms, n_terms);
         sv_status st2 = pauli_apply_impl<T>(s, psi, lam, batches);
         if (st2 != SV_OK) return st2;
-        // f = Re <psi|H psi>
         const int np = kReduceBlocks;
         st2 = ensure_part(s, 2 * (size_t)np);
         if (st2 != SV_OK) return st2;
@@ -1120,6 +1074,58 @@ sv_status sv_adjoint_grad(sv_state s, const sv_gate* gates, int n_gates, const s
             LaunchTimer tm(s, KF_REDUCE);
             HIP_TRY(launch_inner<T>(psi, lam, s->n, s->d_part, np, s->stream));
         }
+
+        // Reverse sweep items: gradient read, then the inverse gate. A grad
+        // item's slot is its position among the grad items (reverse gate order).
+        std::vector<PlanItem> items;
+        std::vector<int> slot_gate;  // grad slot -> gate index
+        items.reserve(hg.size());
+        for (int l = n_gates - 1; l >= 0; l--) {
+            PlanItem it;
+            it.g = dagger(hg[l]);
+            it.g.gen = hg[l].gen;
+            if (hg[l].param >= 0) {
+                it.grad = true;
+                it.grad_slot = (int32_t)slot_gate.size();
+                slot_gate.push_back(l);
+            }
+            items.push_back(it);
+        }
+        fold_diagonals_into_reads(items);
+        std::vector<PlanPass> passes;
+        try {
+            PlanOptions o = plan_options(s->n, s->elem, 2);
+            o.single_gate_sweeps = false;
+            passes = plan_circuit(s->n, items, o, (int)s->elem);
+        } catch (const std::exception& e) {
+            (void)hipStreamSynchronize(s->stream);  // the launches above read psi and write lambda
+            return fail(SV_EINVAL, std::string("planner: ") + e.what());
+        }
+        // Renumber the grad reads pass by pass: the rows of one pass are
+        // contiguous in the device result array, in op order.
+        std::vector<int> rows_per_pass(passes.size(), 0);
+        std::vector<int> row_gate;  // result row -> gate index
+        for (size_t p = 0; p < passes.size(); p++) {
+            int local = 0;
+            for (TileOp& op : passes[p].ops) {
+                if (op.kind == T_GRAD) {
+                    row_gate.push_back(slot_gate[op.slot]);
+                    op.slot = local++;
+                } else if (op.kind == T_GRADZ) {
+                    for (int e = 0; e < op.cnt; e++) {
+                        ReadZ z;
+                        std::memcpy(&z, &passes[p].phase[op.aux + e], sizeof(z));
+                        row_gate.push_back(slot_gate[z.slot]);
+                        z.slot = local++;
+                        std::memcpy(&passes[p].phase[op.aux + e], &z, sizeof(z));
+                    }
+                }
+            }
+            rows_per_pass[p] = local;
+        }
+        const int n_grad = (int)row_gate.size();
+
+        // f = Re <psi|H psi>
         st2 = finish_rows(s, 2, np);
         if (st2 != SV_OK) return st2;
         const double f = s->h_res[0];

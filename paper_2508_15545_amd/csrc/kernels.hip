@@ -104,6 +104,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep1(T* __restrict__ psi, uint64
     }
 }
 
+// The same without controls: the pair index gains one zero bit at k, a
+// shift and a mask instead of the general insertion.
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_sweep1_plain(T* __restrict__ psi, uint64_t npairs, int k, T u00,
+                                                           T u01, T u10, T u11)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t kb = 1ull << k, lo = kb - 1;
+    T x[P], y[P];
+    uint64_t i0[P];
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        i0[r] = ((p & ~lo) << 1) | (p & lo);
+        if (p < npairs) {
+            x[r] = ld_nt(psi + i0[r]);
+            y[r] = ld_nt(psi + (i0[r] | kb));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        if (p < npairs) {
+            st_nt(psi + i0[r], cmul2(u00, x[r], u01, y[r]));
+            st_nt(psi + (i0[r] | kb), cmul2(u10, x[r], u11, y[r]));
+        }
+    }
+}
+
 // Low targets without controls (2^k < 32): every lane loads one amplitude,
 // so each wave reads and writes whole contiguous runs, and takes the
 // partner amplitude i ^ 2^k from lane (lane ^ 2^k) of the same wave. Each
@@ -164,6 +193,12 @@ hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
             constexpr int P = decltype(pc)::value;
             hipLaunchKernelGGL((k_sweep1_lane<T, P>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi,
                                N, k, u00, u01, u10, u11);
+        });
+    } else if (g.ctrl == 0) {
+        with_per_thread(npairs, k < 20 ? 1 : 4, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL((k_sweep1_plain<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st,
+                               psi, npairs, k, u00, u01, u10, u11);
         });
     } else {
         with_per_thread(npairs, k < 20 ? 1 : 4, [&](auto pc) {
@@ -228,9 +263,60 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(T* __restrict__ psi, uint64
     }
 }
 
+// SWAP of qubits a and c (controls allowed): only the amplitudes whose bits
+// a and c differ move, so each of the 2^(n-2) pairs (i | 2^a, i | 2^c) with
+// bits a, c of i clear is read and written once (2^n amplitudes of traffic,
+// half that of a 4x4 sweep).
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_sweep_swap(T* __restrict__ psi, uint64_t npairs, int qa, int qc,
+                                                         Ins ins, uint64_t ctrl)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t ba = 1ull << qa, bc = 1ull << qc;
+    T x[P], y[P];
+    uint64_t i0[P];
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        i0[r] = insert_zeros(p < npairs ? p : 0, ins) | ctrl;
+        if (p < npairs) {
+            x[r] = ld_nt(psi + (i0[r] | ba));
+            y[r] = ld_nt(psi + (i0[r] | bc));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        if (p < npairs) {
+            st_nt(psi + (i0[r] | ba), y[r]);
+            st_nt(psi + (i0[r] | bc), x[r]);
+        }
+    }
+}
+
+static bool is_swap_matrix(const HostGate& g)
+{
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            const bool one = (r == c && (r == 0 || r == 3)) || (r == 1 && c == 2) || (r == 2 && c == 1);
+            if (g.m[4 * r + c] != cd(one ? 1.0 : 0.0, 0.0)) return false;
+        }
+    return true;
+}
+
 template <typename T>
 hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
 {
+    if (is_swap_matrix(g)) {
+        const Ins ins = make_ins(g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]));
+        const uint64_t npairs = 1ull << (n - ins.cnt);
+        with_per_thread(npairs, 2, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL((k_sweep_swap<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st,
+                               psi, npairs, g.q[0], g.q[1], ins, g.ctrl);
+        });
+        return hipGetLastError();
+    }
     const uint64_t mask = g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]);
     const Ins ins = make_ins(mask);
     const uint64_t nquads = 1ull << (n - ins.cnt);
@@ -639,6 +725,58 @@ hipError_t launch_pauli_apply(const T* psi, T* dst, int n, const TermBatch& tb, 
     return hipGetLastError();
 }
 
+// The same for up to kBatchesPerLaunch x-mask groups in one pass: every
+// output sums its terms from all the groups in FP64 registers and is written
+// once (added to dst when accumulating).
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_pauli_apply_multi(const T* __restrict__ psi, T* __restrict__ dst,
+                                                                int n, TermBatchSet set, int accumulate)
+{
+    const uint64_t N = 1ull << n;
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t j = base + (uint64_t)r * kThreads;
+        if (j >= N) continue;
+        double outr = 0, outi = 0;
+        if (accumulate) to_double(dst[j], outr, outi);
+        for (int b = 0; b < set.count; b++) {
+            const TermBatch& tb = set.b[b];
+            const uint64_t j2 = j ^ tb.x_mask;
+            double vr, vi;
+            to_double(psi[j2], vr, vi);
+            double cr = 0, ci = 0;
+            for (int t = 0; t < tb.n_terms; t++) {
+                const double sg = (__popcll(j2 & tb.z_mask[t]) & 1) ? -1.0 : 1.0;
+                cr += sg * tb.coeff_re[t];
+                ci += sg * tb.coeff_im[t];
+            }
+            outr += cr * vr - ci * vi;
+            outi += cr * vi + ci * vr;
+        }
+        T o;
+        o.x = (typename RealOf<T>::type)outr;
+        o.y = (typename RealOf<T>::type)outi;
+        dst[j] = o;
+    }
+}
+
+template <typename T>
+hipError_t launch_pauli_apply_multi(const T* psi, T* dst, int n, const TermBatch* batches, int count,
+                                    bool accumulate, hipStream_t st)
+{
+    if (count < 1 || count > kBatchesPerLaunch) return hipErrorInvalidValue;
+    TermBatchSet set{};
+    set.count = count;
+    for (int b = 0; b < count; b++) set.b[b] = batches[b];
+    with_per_thread(1ull << n, 4, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_pauli_apply_multi<T, P>), dim3(grid_for(1ull << n, kThreads * P)), dim3(kThreads), 0,
+                           st, psi, dst, n, set, accumulate ? 1 : 0);
+    });
+    return hipGetLastError();
+}
+
 // <a|b> = sum conj(a_j) b_j -> partials rows 0 (re) and 1 (im), n_part each.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_inner(const T* __restrict__ a, const T* __restrict__ b, int n,
@@ -824,6 +962,7 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
     template hipError_t launch_block_pass<T>(T*, T*, int, int, const PassHdr*, const TileOp*, const T*, int, \
                                              double*, int64_t, hipStream_t);                                \
     template hipError_t launch_pauli_expect<T>(const T*, int, const TermBatch&, double*, int, hipStream_t);  \
+    template hipError_t launch_pauli_apply_multi<T>(const T*, T*, int, const TermBatch*, int, bool, hipStream_t); \
     template hipError_t launch_pauli_apply<T>(const T*, T*, int, const TermBatch&, bool, hipStream_t);        \
     template hipError_t launch_inner<T>(const T*, const T*, int, double*, int, hipStream_t);                \
     template hipError_t launch_grad_sweep<T>(const T*, const T*, int, int, int, double*, int, hipStream_t);

@@ -327,6 +327,16 @@ hipError_t launch_pauli_expect(const T* psi, int n, const TermBatch& tb, double*
 template <typename T>
 hipError_t launch_pauli_apply(const T* psi, T* dst, int n, const TermBatch& tb, bool accumulate,
                               hipStream_t st);
+// Up to kBatchesPerLaunch x-mask groups in one pass over the state.
+constexpr int kBatchesPerLaunch = 8;
+struct TermBatchSet {
+    int32_t count;
+    int32_t pad;
+    TermBatch b[kBatchesPerLaunch];
+};
+template <typename T>
+hipError_t launch_pauli_apply_multi(const T* psi, T* dst, int n, const TermBatch* batches, int count,
+                                    bool accumulate, hipStream_t st);
 template <typename T>
 hipError_t launch_inner(const T* a, const T* b, int n, double* partials, int n_part, hipStream_t st);
 template <typename T>
