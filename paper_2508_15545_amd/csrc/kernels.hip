@@ -174,9 +174,101 @@ __global__ __launch_bounds__(kThreads) void k_sweep1_lane(T* __restrict__ psi, u
     }
 }
 
+// Gates whose qubits (targets and controls) all lie among the lowest five:
+// their pairs and quadruples sit inside groups of 32 lanes, and a sweep over
+// only the touched amplitudes would use a fraction of each 128-byte line.
+// One coalesced pass instead: every lane loads its amplitude, takes the
+// partners of its quadruple by lane shuffles, writes its own output row, and
+// writes its amplitude back unchanged where the controls are not all 1.
+// KIND 0: 2x2 on qa; KIND 1: 4x4 on (qa, qc), index bit(qa) + 2 bit(qc);
+// KIND 2: diagonal d[bit(qa) + 2 bit(qc)] (qa / qc < 0: bit 0).
+constexpr int kLaneQubits = 5;
+
+// A 4x4 (or 2x2, or diagonal) complex matrix by value, (re, im) pairs.
+struct Mat4 {
+    double v[32];
+};
+
+template <typename T, int P, int KIND>
+__global__ __launch_bounds__(kThreads) void k_gate_lane(T* __restrict__ psi, uint64_t N, int qa, int qc,
+                                                        uint32_t ctrl, Mat4 m)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    using R = typename RealOf<T>::type;
+    auto U = [&](int e) {
+        T u;
+        u.x = (R)m.v[2 * e];
+        u.y = (R)m.v[2 * e + 1];
+        return u;
+    };
+    const uint32_t li = threadIdx.x;  // the index's low bits (kThreads is a multiple of 32)
+    const bool on = (li & ctrl) == ctrl;
+    const int ba = qa >= 0 ? (int)((li >> qa) & 1) : 0;
+    const int bc = qc >= 0 ? (int)((li >> qc) & 1) : 0;
+    const int row = ba + 2 * bc;
+    T v[P];
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t i = base + (uint64_t)r * kThreads;
+        if (i < N) v[r] = ld_nt(psi + i);
+    }
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t i = base + (uint64_t)r * kThreads;
+        T out = v[r];
+        if constexpr (KIND == 0) {
+            const T y = shfl_xor_amp(v[r], 1 << qa);  // every lane takes part in the shuffle
+            const T own = ba ? U(3) : U(0), par = ba ? U(2) : U(1);
+            if (on) out = cmul2(own, v[r], par, y);
+        } else if constexpr (KIND == 1) {
+            // x[e] for e = row ^ f: the partner across the bits set in f
+            const T p1 = shfl_xor_amp(v[r], 1 << qa), p2 = shfl_xor_amp(v[r], 1 << qc),
+                    p3 = shfl_xor_amp(v[r], (1 << qa) | (1 << qc));
+            if (on) {
+                const T a0 = cmul2(U(4 * row + row), v[r], U(4 * row + (row ^ 1)), p1);
+                const T a1 = cmul2(U(4 * row + (row ^ 2)), p2, U(4 * row + (row ^ 3)), p3);
+                out.x = a0.x + a1.x;
+                out.y = a0.y + a1.y;
+            }
+        } else {
+            if (on) out = cmul(U(row), v[r]);
+        }
+        if (i < N) st_nt(psi + i, out);
+    }
+}
+
+// True when every qubit of g (targets and controls) is below kLaneQubits and
+// the state has whole waves of amplitudes.
+static bool lane_gate(const HostGate& g, int n)
+{
+    uint64_t bits = g.ctrl;
+    if (g.q[0] >= 0) bits |= 1ull << g.q[0];
+    if (g.q[1] >= 0) bits |= 1ull << g.q[1];
+    return n >= 8 && (bits >> kLaneQubits) == 0;
+}
+
+template <typename T, int KIND>
+static hipError_t launch_gate_lane(T* psi, int n, const HostGate& g, hipStream_t st)
+{
+    const uint64_t N = 1ull << n;
+    Mat4 m{};
+    const int cnt = KIND == 0 ? 4 : KIND == 1 ? 16 : 4;
+    for (int e = 0; e < cnt; e++) {
+        m.v[2 * e] = g.m[e].real();
+        m.v[2 * e + 1] = g.m[e].imag();
+    }
+    with_per_thread(N, 1, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        hipLaunchKernelGGL((k_gate_lane<T, P, KIND>), dim3(grid_for(N, kThreads * P)), dim3(kThreads), 0, st, psi,
+                           N, g.q[0], g.q[1], (uint32_t)g.ctrl, m);
+    });
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
 {
+    if (g.ctrl != 0 && lane_gate(g, n)) return launch_gate_lane<T, 0>(psi, n, g, st);
     // Measured on MI355X at 29 qubits: one pair (or amplitude) per thread is
     // fastest while the partner stride is below 2^20 amplitudes (more,
     // smaller workgroups walk memory more evenly: 6.8 TB/s for the lane
@@ -214,9 +306,6 @@ hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
 // 4x4 update of every quadruple {i, i|2^a, i|2^c, i|2^a|2^c} with bits a, c
 // of i clear (index bit(a) + 2 bit(c)) and all control bits set.
 
-struct Mat4 {
-    double v[32];
-};
 
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_sweep2(T* __restrict__ psi, uint64_t nquads, int qa, int qc,
@@ -307,6 +396,7 @@ static bool is_swap_matrix(const HostGate& g)
 template <typename T>
 hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
 {
+    if (lane_gate(g, n)) return launch_gate_lane<T, 1>(psi, n, g, st);
     if (is_swap_matrix(g)) {
         const Ins ins = make_ins(g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]));
         const uint64_t npairs = 1ull << (n - ins.cnt);
@@ -366,6 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_diag(T* __restrict__ psi, ui
 template <typename T>
 hipError_t launch_sweep_diag(T* psi, int n, const HostGate& g, hipStream_t st)
 {
+    if (lane_gate(g, n)) return launch_gate_lane<T, 2>(psi, n, g, st);
     const Ins ins = make_ins(g.ctrl);
     const uint64_t count = 1ull << (n - ins.cnt);
     with_per_thread(count, 4, [&](auto pc) {

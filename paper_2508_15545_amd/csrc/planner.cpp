@@ -967,7 +967,8 @@ void merge_diagonals(PlanPass& pp, int r)
 // Z reads of the adjoint sweep (Im <lambda|Z_q|phi>) commute with every op
 // that does not act densely on q (diagonal gates, other reads, gates on other
 // qubits), so each read may wait until such an op or the end of the pass.
-// Reads that wait together become one op that passes over the registers once:
+// When one waiting read has to be taken, all are taken there, and reads
+// taken together become one op that passes over the registers once:
 // with p_k = Im(conj(lambda_k) phi_k), a read of window bit j is
 // sum_k (-1)^(k_j) p_k, and a read of a thread bit or of a qubit outside the
 // block is +-sum_k p_k (the same sums, in the same order, as one read alone).
@@ -1020,12 +1021,18 @@ void group_z_reads(PlanPass& pp, int r)
                 continue;
             }
             if (t.kind != T_GRAD) {
-                // the reads on a qubit this op changes go first
+                // when this op changes the qubit of a waiting read, every
+                // waiting read is taken here, before it: each has waited only
+                // past ops that are not dense on its qubit, so any point up to
+                // its own qubit's next dense op is right for it, and reads
+                // taken together share one pass over the registers
                 const uint32_t dp = dense_positions(t);
-                std::vector<TileOp> now, keep;
-                for (const TileOp& g : pending) (g.a >= 0 && (dp >> g.a) & 1u ? now : keep).push_back(g);
-                emit(si, now);
-                pending.swap(keep);
+                bool hit = false;
+                for (const TileOp& g : pending) hit = hit || (g.a >= 0 && ((dp >> g.a) & 1u));
+                if (hit) {
+                    emit(si, pending);
+                    pending.clear();
+                }
             }
             out[si].push_back(t);
         }

@@ -513,3 +513,34 @@ def test_complex64_matrix_core_4x4(qv, monkeypatch, kind, n, seed):
         got[knob] = host(st)
         assert maxabs(got[knob], want) <= 1e-5, knob
     assert maxabs(got["1"], got["0"]) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_low_qubit_sweeps(qv, dtype):
+    """Unfused gates whose qubits all lie among the lowest five (one
+    coalesced lane pass): every two-qubit op on every ordered pair of
+    qubits 0..4, one-qubit matrices with one and two low controls, and a
+    controlled one-qubit gate mixing low and high qubits."""
+    n = 10
+    rng = C.rng_for(77)
+    psi = C.random_state(n, 12)
+    gates = []
+    for a in range(5):
+        for b in range(5):
+            if a == b:
+                continue
+            gates.append(C.gate("cx", a, b))
+            gates.append(C.gate("cz", a, b))
+            gates.append(C.gate("cp", a, b, params=(1.1,)))
+            gates.append(C.gate("swap", a, b))
+            gates.append(C.gate("mat2", a, b, params=C.matrix_params(C.random_unitary(4, rng))))
+    want = psi.copy()
+    for g in gates:
+        want = oracle.apply_gate(want, n, g)
+    st = load(qv, n, psi, dtype)
+    st.apply(gates, fused=False)
+    for (t, ctrls) in [(0, (3,)), (4, (0, 2)), (2, (1,)), (1, (4, 9)), (7, (0,))]:
+        u = C.random_unitary(2, rng)
+        st.apply_matrix([t], u, controls=ctrls)
+        want = oracle.apply_1q(want, n, t, u, ctrl_mask=sum(1 << c for c in ctrls))
+    assert maxabs(host(st), want) <= TOL[dtype]
