@@ -219,12 +219,16 @@ __device__ __forceinline__ f2 flip_sign(f2 x, uint32_t m)
     return x;
 }
 
-// Register permutations (X, CNOT, SWAP) multiply by `one` (always 1.0,
-// exact) so that they are computed into the registers they overwrite: a
-// plain move would be compiled as a renaming, and every path through the op
-// loop would then have to copy the whole state back into place.
+// A register copy the compiler cannot see through: a multiplication by
+// `one`, 1.0 read at run time (exact; four cycles per FP64 value, the cost
+// of a 64-bit move). The op loop alternates between two register sets, and
+// each op must define every register of the set it writes: a plain
+// assignment would let the register allocator merge the two sets along that
+// path, and every other op would then end in a copy of the whole state.
+// Permutations (X, CNOT, SWAP), registers an op leaves alone, and ops that
+// only read the state write through this.
 template <typename T>
-__device__ __forceinline__ T keep(T x, typename RealOf<T>::type one)
+__device__ __forceinline__ T fresh(T x, typename RealOf<T>::type one)
 {
     T r;
     r.x = x.x * one;
@@ -232,8 +236,20 @@ __device__ __forceinline__ T keep(T x, typename RealOf<T>::type one)
     return r;
 }
 
+// Every register through fresh (with two register sets; with one set the
+// registers stay where they are).
+template <bool PP, typename T, int NS, int R>
+__device__ __forceinline__ void fresh_all(T (&v)[NS][R], typename RealOf<T>::type z)
+{
+    if constexpr (!PP) return;
+#pragma unroll
+    for (int s = 0; s < NS; s++)
+#pragma unroll
+        for (int k = 0; k < R; k++) v[s][k] = fresh(v[s][k], z);
+}
+
 template <typename T, int RB, int NS, int J, bool CTRL>
-__device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type one)
+__device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type z)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
@@ -247,8 +263,8 @@ __device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm, type
                 v[s][k] = on ? y : x;
                 v[s][k1] = on ? x : y;
             } else {
-                v[s][k] = keep(y, one);
-                v[s][k1] = keep(x, one);
+                v[s][k] = fresh(y, z);
+                v[s][k1] = fresh(x, z);
             }
         }
     }
@@ -256,18 +272,20 @@ __device__ __forceinline__ void reg_xperm(T (&v)[NS][1 << RB], uint32_t cm, type
 
 // CNOT with target window bit JT and control window bit JC: swap the
 // register pairs whose control bit is set.
-template <typename T, int RB, int NS, int JT, int JC>
-__device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB], typename RealOf<T>::type one)
+template <bool PP, typename T, int RB, int NS, int JT, int JC>
+__device__ __forceinline__ void reg_cx(T (&v)[NS][1 << RB], typename RealOf<T>::type z)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
-        if ((k & (1 << JT)) || !(k & (1 << JC))) continue;
+        if (k & (1 << JT)) continue;
         const int k1 = k | (1 << JT);
+        const bool swap = (k & (1 << JC)) != 0;
+        if (!swap && !PP) continue;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             const T x = v[s][k], y = v[s][k1];
-            v[s][k] = keep(y, one);
-            v[s][k1] = keep(x, one);
+            v[s][k] = fresh(swap ? y : x, z);
+            v[s][k1] = fresh(swap ? x : y, z);
         }
     }
 }
@@ -340,13 +358,13 @@ __device__ __forceinline__ void reg_dense2_mfma(f2 (&v)[1][1 << RB], const f2* _
     }
 }
 
-template <typename T, int RB, int NS, int J0, int J1, bool CTRL>
-__device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type one)
+template <bool PP, typename T, int RB, int NS, int J0, int J1, bool CTRL>
+__device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typename RealOf<T>::type z)
 {
 #pragma unroll
     for (int k = 0; k < (1 << RB); k++) {
         if (k & ((1 << J0) | (1 << J1))) continue;
-        const int a = k | (1 << J0), c = k | (1 << J1);
+        const int a = k | (1 << J0), c = k | (1 << J1), d = a | c;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             const T x = v[s][a], y = v[s][c];
@@ -355,8 +373,13 @@ __device__ __forceinline__ void reg_swap(T (&v)[NS][1 << RB], uint32_t cm, typen
                 v[s][a] = on ? y : x;
                 v[s][c] = on ? x : y;
             } else {
-                v[s][a] = keep(y, one);
-                v[s][c] = keep(x, one);
+                v[s][a] = fresh(y, z);
+                v[s][c] = fresh(x, z);
+            }
+            // the pairs whose two bits agree stay
+            if constexpr (PP) {
+                v[s][k] = fresh(v[s][k], z);
+                v[s][d] = fresh(v[s][d], z);
             }
         }
     }
@@ -429,7 +452,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     const int b = hdr->b;
     const int nloc = 1 << b;
     const int tb = b - RB;
-    // 1.0, read at run time so that the compiler keeps the multiplications
+    // two register sets in the op loop (see there)
+    constexpr bool PP = sizeof(T) == 16 || NS == 2;
+    // 1.0, read at run time (see fresh)
     const typename RealOf<T>::type one = (typename RealOf<T>::type)(hdr->pad + 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -524,15 +549,15 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #pragma unroll
             for (int j = 0; j < kMaxRegBits; j++) cur_w[j] = w_new[j];
         }
-        // The per-op fields of the next op are loaded while the current op
-        // runs, so that each op waits for one round of scalar loads (its
-        // matrix) instead of three.
         const TileOp* sop = po + sh.op_begin;
         const int nops = sh.n_ops;
-        OpHot cur = op_hot(sop);
-        for (int o = 0; o < nops; o++) {
-            const OpHot nxt = op_hot(sop + (o + 1 < nops ? o + 1 : o));
-            const TileOp& op = sop[o];  // the other fields, read where a case needs them
+        // Ops alternate between two register sets (vb = op(v), then
+        // v = op(vb)): each op writes its results into the other set, so a
+        // dense update is not copied back into the registers it read before
+        // the next op (with one set, every op ends in a copy of the state).
+        // The complex64 single-state kernel keeps one set: the second would
+        // cost it registers below its five waves per SIMD.
+        auto op_body = [&](T (&v)[NS][R], const OpHot& cur, const TileOp& op) __attribute__((always_inline)) {
             if ((base & cur.gctrl) == cur.gctrl) {  // uniform over the block
             const int code = cur.code;
             // registers the op acts on (all, for ops without local controls)
@@ -540,12 +565,12 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
             switch (code) {
 #define QV_C1(BASE, J, STMT) \
     case BASE + J:           \
-        if constexpr (J < RB) { STMT; } \
+        if constexpr (J < RB) { STMT; } else { fresh_all<PP>(v, one); } \
         break;
 #define QV_ALL1(BASE, F) QV_C1(BASE, 0, F(0)) QV_C1(BASE, 1, F(1)) QV_C1(BASE, 2, F(2)) QV_C1(BASE, 3, F(3)) QV_C1(BASE, 4, F(4))
 #define QV_C2(BASE, A, B, F) \
     case BASE + 5 * A + B:   \
-        if constexpr (A < RB && B < RB && A != B) { F(A, B); } \
+        if constexpr (A < RB && B < RB && A != B) { F(A, B); } else { fresh_all<PP>(v, one); } \
         break;
 #define QV_PAIRS(BASE, F) \
     QV_C2(BASE, 0, 1, F) QV_C2(BASE, 0, 2, F) QV_C2(BASE, 0, 3, F) QV_C2(BASE, 0, 4, F) QV_C2(BASE, 1, 2, F) \
@@ -559,12 +584,12 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #define F_D1C(J) reg_dense1<T, RB, NS, J, true>(v, QV_M2, cm)
 #define F_X(J) reg_xperm<T, RB, NS, J, false>(v, cm, one)
 #define F_XC(J) reg_xperm<T, RB, NS, J, true>(v, cm, one)
-#define F_CX(A, B) reg_cx<T, RB, NS, A, B>(v, one)
+#define F_CX(A, B) reg_cx<PP, T, RB, NS, A, B>(v, one)
 #define F_D2(A, B) reg_dense2<T, RB, NS, A, B, false>(v, mats + cur.mat, cm)
 #define F_D2C(A, B) reg_dense2<T, RB, NS, A, B, true>(v, mats + cur.mat, cm)
-#define F_SW(A, B) reg_swap<T, RB, NS, A, B, false>(v, cm, one)
-#define F_D2M(A, B) if constexpr (MF && sizeof(T) == 8 && NS == 1) { reg_dense2_mfma<RB, A, B>(v, mats + cur.mat, lane); }
-#define F_SWC(A, B) reg_swap<T, RB, NS, A, B, true>(v, cm, one)
+#define F_SW(A, B) reg_swap<PP, T, RB, NS, A, B, false>(v, cm, one)
+#define F_D2M(A, B) if constexpr (MF && sizeof(T) == 8 && NS == 1) { reg_dense2_mfma<RB, A, B>(v, mats + cur.mat, lane); } else { fresh_all<PP>(v, one); }
+#define F_SWC(A, B) reg_swap<PP, T, RB, NS, A, B, true>(v, cm, one)
                 QV_ALL1(RC_D1, F_D1)
                 QV_ALL1(RC_D1C, F_D1C)
                 QV_ALL1(RC_X, F_X)
@@ -608,10 +633,9 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 const uint32_t tsign = (cur_tl & cur.tctrl) == cur.tctrl ? 0x80000000u : 0u;
 #pragma unroll
                 for (int k = 0; k < R; k++) {
-                    if (cur.kmask & (1u << k)) {
+                    const bool flip = (cur.kmask >> k) & 1u;
 #pragma unroll
-                        for (int s = 0; s < NS; s++) v[s][k] = flip_sign(v[s][k], tsign);
-                    }
+                    for (int s = 0; s < NS; s++) v[s][k] = flip ? flip_sign(v[s][k], tsign) : PP ? fresh(v[s][k], one) : v[s][k];
                 }
                 break;
             }
@@ -697,6 +721,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                     const double acc = wave_total((double)pacc);
                     if (lane == 0) red[op.slot * 8 + wave] = acc;
                 }
+                fresh_all<PP>(v, one);
                 break;
             }
             case RC_GZM: {
@@ -734,6 +759,7 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                         if (lane == 0) red[zslot * 8 + wave] = val;
                     }
                 }
+                fresh_all<PP>(v, one);
                 break;
             }
 #define F_G(J)                                                   \
@@ -741,7 +767,8 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         double acc = reg_grad_xy<T, RB, J>(v, (double)mats[cur.mat].x, (double)mats[cur.mat].y); \
         acc = wave_total(acc);                                     \
         if (lane == 0) red[op.slot * 8 + wave] = acc;            \
-    }
+    }                                                            \
+    fresh_all<PP>(v, one)
                 QV_ALL1(RC_GXY, F_G)
 #undef F_G
 #undef F_D1
@@ -760,10 +787,51 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
 #undef QV_C2
 #undef QV_ALL1
 #undef QV_C1
-            default: break;
+            default: fresh_all<PP>(v, one); break;
             }
+            } else {
+                fresh_all<PP>(v, one);
             }
-            cur = nxt;
+        };
+        auto apply_op = [&](const T (&src)[NS][R], T (&dst)[NS][R], const OpHot& cur,
+                            const TileOp& op) __attribute__((always_inline)) {
+            T w[NS][R];
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+#pragma unroll
+                for (int k = 0; k < R; k++) w[s][k] = src[s][k];
+            op_body(w, cur, op);
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+#pragma unroll
+                for (int k = 0; k < R; k++) dst[s][k] = w[s][k];
+        };
+        // The hot fields of the next op are loaded while the current op runs,
+        // so that each op waits for one round of scalar loads (its matrix)
+        // instead of three.
+        OpHot cur = op_hot(sop);
+        if constexpr (PP) {
+            T vb[NS][R];
+            for (int o = 0; o < nops; o += 2) {
+                const OpHot h1 = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+                apply_op(v, vb, cur, sop[o]);
+                const OpHot h2 = op_hot(sop + (o + 2 < nops ? o + 2 : o));
+                if (o + 1 < nops) {
+                    apply_op(vb, v, h1, sop[o + 1]);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < NS; s++)
+#pragma unroll
+                        for (int k = 0; k < R; k++) v[s][k] = fresh(vb[s][k], one);
+                }
+                cur = h2;
+            }
+        } else {
+            for (int o = 0; o < nops; o++) {
+                const OpHot nxt = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+                op_body(v, cur, sop[o]);
+                cur = nxt;
+            }
         }
     }
 
