@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqvec.so")
-SOURCES = ["kernels.hip", "kernels_block.hip", "gates.cpp", "planner.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_block_c128.hip", "kernels_block_c64.hip", "gates.cpp", "planner.cpp", "capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept off: the compiler must not form them.
@@ -20,24 +20,28 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
-def _compile(src: str, obj: str, verbose: bool) -> None:
+def _compile_cmd(src: str, obj: str) -> list:
     path = os.path.join(CSRC, src)
     lang = ["-x", "hip"]  # every source goes through the HIP driver (kernels and host API)
-    cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *lang, "-c", path, "-o", obj]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    return [HIPCC, *COMMON, *DEVICE_FLAGS, *lang, "-c", path, "-o", obj]
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libqvec.so. Always recompiles."""
+    """Compile every source (in parallel, one process per source) and link
+    libqvec.so. Always recompiles."""
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
-    objs = []
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
-        _compile(src, obj, verbose)
+        cmd = _compile_cmd(src, obj)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -976,9 +976,16 @@ hipError_t launch_block_reg(T* s0, T* s1, int n, int n_states, int rb, const Pas
     return hipErrorInvalidValue;
 }
 
+// QV_BLOCK_ELEM (16 or 8) limits a translation unit to one element type, so
+// that the two sets of kernels compile in parallel (kernels_block_c128.hip,
+// kernels_block_c64.hip); without it this file instantiates both.
+#if !defined(QV_BLOCK_ELEM) || QV_BLOCK_ELEM == 16
 template hipError_t launch_block_reg<d2>(d2*, d2*, int, int, int, const PassHdr*, const StageHdr*, const TileOp*,
                                          const d2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
+#endif
+#if !defined(QV_BLOCK_ELEM) || QV_BLOCK_ELEM == 8
 template hipError_t launch_block_reg<f2>(f2*, f2*, int, int, int, const PassHdr*, const StageHdr*, const TileOp*,
                                          const f2*, const PhaseTerm*, int, double*, int64_t, hipStream_t);
+#endif
 
 }  // namespace qv
