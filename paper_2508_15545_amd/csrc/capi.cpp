@@ -441,6 +441,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.b = default_block_qubits(n, (int)elem, n_states);
     // keep 128-byte runs contiguous in memory: 8 complex128 / 16 complex64
     o.coalesce = elem == 16 ? 3 : 4;
+    const char* co = std::getenv("QVEC_COALESCE");  // lowest qubits kept in every block (2..6)
+    if (co && co[0] >= '2' && co[0] <= '6' && co[1] == 0) o.coalesce = co[0] - '0';
     const char* env = std::getenv("QVEC_BLOCK_KERNEL");
     const bool reg = g_reg_kernel && !(env && std::strcmp(env, "lds") == 0);
     o.reg_bits = reg ? reg_bits_for((int)elem, n_states) : 0;
