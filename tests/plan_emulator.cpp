@@ -257,6 +257,7 @@ int main(int argc, char** argv)
     PlanOptions o;
     o.b = std::min(default_block_qubits(n, elem, 1), std::min(n, 12));
     o.coalesce = elem == 16 ? 3 : 4;
+    if (argc > 4 && std::atoi(argv[4]) > 0) o.coalesce = std::atoi(argv[4]);  // the QVEC_COALESCE knob
     o.reg_bits = 4;
     o.lds_elem = elem == 16 ? 8 : elem;
     o.prefuse = true;

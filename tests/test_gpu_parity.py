@@ -160,6 +160,26 @@ def test_qubit_moves_between_passes(qv, monkeypatch, kind, n, seed, dtype):
     assert passes["1"] <= passes["0"] + 1, passes
 
 
+KNOBS = [("QVEC_COALESCE", "2"), ("QVEC_COALESCE", "4"), ("QVEC_COALESCE", "5"), ("QVEC_COALESCE", "6"),
+         ("QVEC_REG_BITS", "3"), ("QVEC_FUSE", "0"), ("QVEC_WAVE_MODE", "0"), ("QVEC_WAVE_MODE", "1"),
+         ("QVEC_BLOCK_QUBITS", "10"), ("QVEC_BLOCK_QUBITS", "11"), ("QVEC_PREFETCH", "1"),
+         ("QVEC_BLOCK_KERNEL", "lds"), ("QVEC_PASS_SELECT", "greedy")]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("knob,value", KNOBS)
+def test_scheduling_knobs_keep_the_state(qv, monkeypatch, knob, value, dtype):
+    """Every scheduling knob changes how the passes are formed or run, never
+    the result: a mixed circuit and a QFT against the oracle under each."""
+    print(f"knob {knob}={value} dtype={dtype}", flush=True)
+    monkeypatch.setenv(knob, value)
+    n = 17
+    for circ, x in ((C.random_mixed_circuit(n, 300, 4), C.random_basis_index(n, 4)), (C.qft(n), 12345)):
+        want = oracle.run(circ, n, x0=x)
+        st = qv.State(n, dtype).set_basis(x).apply(circ)
+        assert maxabs(host(st), want) <= TOL[dtype], (knob, value)
+
+
 # ------------------------------------------------------------ closed forms ---
 
 @pytest.mark.parametrize("dtype", DTYPES)

@@ -63,3 +63,21 @@ def test_planned_passes_equal_gate_by_gate(emulator, kind, n, depth, seed, elem,
                        text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "structure_errors=0" in r.stdout
+
+
+@pytest.mark.parametrize("elem", [16, 8])
+@pytest.mark.parametrize("coalesce", [2, 4, 5, 6])
+@pytest.mark.parametrize("kind,n,depth,seed", [("cx", 18, 8, 4), ("qft", 17, 0, 0), ("mixed", 16, 300, 6)])
+def test_coalescing_knob_plans(emulator, kind, n, depth, seed, elem, coalesce):
+    """Plans with 2 to 6 low qubits kept in every block (QVEC_COALESCE) give
+    the gate-by-gate state."""
+    if kind == "qft":
+        circ = C.qft(n)
+    elif kind == "mixed":
+        circ = C.random_mixed_circuit(n, depth, seed, ops=MIXED_OPS)
+    else:
+        circ = C.random_u3_layers(n, depth, seed, entangler=kind)
+    r = subprocess.run([emulator, str(n), str(elem), "0", str(coalesce)], input=gate_lines(circ),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "structure_errors=0" in r.stdout
