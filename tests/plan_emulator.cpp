@@ -155,6 +155,9 @@ static void run_block_pass(std::vector<C>& psi, int n, const PlanPass& pp)
     }
 }
 
+static int g_slot_bytes = 8;     // exchange slot size of the kernel the plan is for
+static int g_bank_conflicts = 0;  // (mapping, register) pairs whose lowest lanes share a bank row slot
+
 static int check_structure(const std::vector<PlanPass>& passes)
 {
     int bad = 0;
@@ -179,8 +182,53 @@ static int check_structure(const std::vector<PlanPass>& passes)
         };
         bool block_xch = h.final_wave_local == XCH_BLOCK;
         const StageHdr* cur = &h.nat;
+        // Exchange-buffer byte offset of (thread, register) under a mapping,
+        // as the kernel forms it: the slot of the thread part (lds_slot) and
+        // the register's window part from the stage table.
+        auto offset_of = [&](const StageHdr& m, uint32_t tid, uint32_t k) {
+            const uint32_t e = g_slot_bytes == 16 ? 4 : 5;
+            uint32_t tl = 0;
+            for (int i = 0; i < tb; i++) tl |= ((tid >> i) & 1u) << m.tpos[i];
+            return lds_slot(tl, (int)e) * (uint32_t)g_slot_bytes ^ m.woff[k];
+        };
+        // Every exchange: the write of the current mapping fills each slot
+        // once, and the read of the new one finds in each register the
+        // amplitude of its own local index. Lanes 0..2^e-1 of a wave (2^e
+        // slots of 256 / 2^e bytes: one row of LDS banks) that share a row
+        // position are counted as bank conflicts (reported, not required).
+        auto lds_round_trip = [&](const StageHdr& to) {
+            const uint32_t sb = (uint32_t)g_slot_bytes, e = sb == 16 ? 4 : 5;
+            const uint32_t nslots = 1u << b;
+            std::vector<int64_t> buf(nslots, -1);
+            for (uint32_t tid = 0; tid < (1u << tb); tid++)
+                for (uint32_t k = 0; k < (1u << r); k++) {
+                    const uint32_t o = offset_of(*cur, tid, k);
+                    if (o % sb || o / sb >= nslots || buf[o / sb] >= 0) {
+                        std::printf("pass %zu: exchange write collides or leaves the buffer\n", pi);
+                        bad++;
+                        return;
+                    }
+                    buf[o / sb] = index_of(*cur, tid, k);
+                }
+            for (uint32_t tid = 0; tid < (1u << tb); tid++)
+                for (uint32_t k = 0; k < (1u << r); k++) {
+                    const uint32_t o = offset_of(to, tid, k);
+                    if (o / sb >= nslots || buf[o / sb] != (int64_t)index_of(to, tid, k)) {
+                        std::printf("pass %zu: exchange read finds another amplitude\n", pi);
+                        bad++;
+                        return;
+                    }
+                }
+            for (const StageHdr* m : {cur, &to})
+                for (uint32_t k = 0; k < (1u << r); k++) {
+                    uint32_t seen = 0;
+                    for (uint32_t lane = 0; lane < (1u << e); lane++) seen |= 1u << ((offset_of(*m, lane, k) / sb) & ((1u << e) - 1));
+                    if (seen != (uint32_t)((1ull << (1u << e)) - 1)) g_bank_conflicts++;
+                }
+        };
         auto check_xch = [&](const StageHdr& to, int kind) {
             if (kind == XCH_BLOCK) block_xch = true;
+            if (kind != XCH_NONE) lds_round_trip(to);
             if (kind != XCH_WAVE) return;
             for (int w = 0; w < nwaves; w++)
                 if (wave_set(*cur, w) != wave_set(to, w)) {
@@ -260,6 +308,7 @@ int main(int argc, char** argv)
     if (argc > 4 && std::atoi(argv[4]) > 0) o.coalesce = std::atoi(argv[4]);  // the QVEC_COALESCE knob
     o.reg_bits = 4;
     o.lds_elem = elem == 16 ? 8 : elem;
+    g_slot_bytes = o.lds_elem;
     o.prefuse = true;
     o.park = std::atoi(argv[3]) > 0;
     const std::vector<PlanPass> passes = plan_circuit(n, items, o, elem);
@@ -284,6 +333,7 @@ int main(int argc, char** argv)
     }
     double err = 0;
     for (size_t i = 0; i < psi.size(); i++) err = std::max(err, std::abs(psi[i] - ref[i]));
-    std::printf("n=%d elem=%d passes=%zu structure_errors=%d maxerr=%.3e\n", n, elem, passes.size(), bad, err);
+    std::printf("n=%d elem=%d passes=%zu structure_errors=%d bank_conflicts=%d maxerr=%.3e\n", n, elem,
+                passes.size(), bad, g_bank_conflicts, err);
     return (bad == 0 && err < 1e-10) ? 0 : 1;
 }

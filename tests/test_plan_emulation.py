@@ -81,3 +81,4 @@ def test_coalescing_knob_plans(emulator, kind, n, depth, seed, elem, coalesce):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "structure_errors=0" in r.stdout
+
