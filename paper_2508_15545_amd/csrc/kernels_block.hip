@@ -106,6 +106,12 @@ struct OpHot {
     uint64_t gctrl;
 };
 
+// Ops that read the state without changing it (the adjoint's gradient reads).
+__device__ __forceinline__ bool is_read_code(int code)
+{
+    return code == RC_GZ || code == RC_GZM || (code >= RC_GXY && code < RC_GXY + kMaxRegBits);
+}
+
 __device__ __forceinline__ OpHot op_hot(const TileOp* p)
 {
     OpHot h;
@@ -557,6 +563,88 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         // the next op (with one set, every op ends in a copy of the state).
         // The complex64 single-state kernel keeps one set: the second would
         // cost it registers below its five waves per SIMD.
+        // Gradient reads (Im <lambda|G|phi> into the wave's LDS slots) leave
+        // the state as it is; with two register sets they run on whichever
+        // set holds the state, between the ops that change it.
+        auto read_body = [&](const T (&v)[NS][R], const OpHot& cur, const TileOp& op) __attribute__((always_inline)) {
+            if ((base & cur.gctrl) != cur.gctrl) return;  // uniform over the block
+            switch (cur.code) {
+#define QV_C1(BASE, J, STMT) \
+    case BASE + J:           \
+        if constexpr (J < RB) { STMT; } \
+        break;
+#define QV_ALL1(BASE, F) QV_C1(BASE, 0, F(0)) QV_C1(BASE, 1, F(1)) QV_C1(BASE, 2, F(2)) QV_C1(BASE, 3, F(3)) QV_C1(BASE, 4, F(4))
+            case RC_GZ: {
+                if constexpr (NS == 2) {
+                    // per-thread partial in the state's precision, FP64 beyond
+                    typename RealOf<T>::type pacc = 0;
+                    const int a = op.a;
+                    const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
+                    uint32_t tlx = cur_tl;
+                    asm volatile("" : "+v"(tlx));
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        const uint32_t l = tlx | window_part<RB>(k, cur_w);
+                        const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
+                        const T f = v[0][k], m = v[1][k];
+                        const auto im = m.x * f.y - m.y * f.x;
+                        pacc += bit ? -im : im;
+                    }
+                    const double acc = wave_total((double)pacc);
+                    if (lane == 0) red[op.slot * 8 + wave] = acc;
+                }
+                break;
+            }
+            case RC_GZM: {
+                // several Z reads: p_k = Im(conj(lambda_k) phi_k) once, then a
+                // read of window bit j is sum_k (-1)^(k_j) p_k and a read of a
+                // thread bit or an outer qubit is +-sum_k p_k
+                if constexpr (NS == 2) {
+                    // per-thread sums in the state's precision, FP64 beyond
+                    using RT = typename RealOf<T>::type;
+                    RT S = 0, D[RB];
+#pragma unroll
+                    for (int j = 0; j < RB; j++) D[j] = 0;
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        const T f = v[0][k], m = v[1][k];
+                        const RT p = m.x * f.y - m.y * f.x;
+                        S += p;
+#pragma unroll
+                        for (int j = 0; j < RB; j++) D[j] += ((k >> j) & 1) ? -p : p;
+                    }
+                    const ReadZ* rz = reinterpret_cast<const ReadZ*>(phase + op.aux);
+                    const uint32_t utid = (uint32_t)tid;
+                    for (int e = 0; e < op.cnt; e++) {
+                        const int zj = rz[e].j, ztb = rz[e].tbit, zoa = rz[e].oa, zslot = rz[e].slot;
+                        RT pv;
+                        if (zj >= 0) {
+                            pv = D[0];
+#pragma unroll
+                            for (int j = 1; j < RB; j++) pv = zj == j ? D[j] : pv;
+                        } else {
+                            const bool bit = ztb >= 0 ? ((utid >> ztb) & 1u) != 0 : ((base >> zoa) & 1ull) != 0;
+                            pv = bit ? -S : S;
+                        }
+                        const double val = wave_total((double)pv);
+                        if (lane == 0) red[zslot * 8 + wave] = val;
+                    }
+                }
+                break;
+            }
+#define F_G(J)                                                                                        \
+    if constexpr (NS == 2) {                                                                          \
+        double acc = reg_grad_xy<T, RB, J>(v, (double)mats[cur.mat].x, (double)mats[cur.mat].y);      \
+        acc = wave_total(acc);                                                                        \
+        if (lane == 0) red[op.slot * 8 + wave] = acc;                                                 \
+    }
+                QV_ALL1(RC_GXY, F_G)
+#undef F_G
+#undef QV_ALL1
+#undef QV_C1
+            default: break;
+            }
+        };
         auto op_body = [&](T (&v)[NS][R], const OpHot& cur, const TileOp& op) __attribute__((always_inline)) {
             if ((base & cur.gctrl) == cur.gctrl) {  // uniform over the block
             const int code = cur.code;
@@ -702,72 +790,13 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 }
                 break;
             }
-            case RC_GZ: {
-                if constexpr (NS == 2) {
-                    // per-thread partial in the state's precision, FP64 beyond
-                    typename RealOf<T>::type pacc = 0;
-                    const int a = op.a;
-                    const int ua = a < 0 ? (int)((base >> op.oa) & 1) : 0;
-                    uint32_t tlx = cur_tl;
-                    asm volatile("" : "+v"(tlx));
-#pragma unroll
-                    for (int k = 0; k < R; k++) {
-                        const uint32_t l = tlx | window_part<RB>(k, cur_w);
-                        const int bit = a >= 0 ? (int)((l >> a) & 1) : ua;
-                        const T f = v[0][k], m = v[1][k];
-                        const auto im = m.x * f.y - m.y * f.x;
-                        pacc += bit ? -im : im;
-                    }
-                    const double acc = wave_total((double)pacc);
-                    if (lane == 0) red[op.slot * 8 + wave] = acc;
-                }
+            case RC_GZ:
+            case RC_GZM:
+                read_body(v, cur, op);
                 fresh_all<PP>(v, one);
                 break;
-            }
-            case RC_GZM: {
-                // several Z reads: p_k = Im(conj(lambda_k) phi_k) once, then a
-                // read of window bit j is sum_k (-1)^(k_j) p_k and a read of a
-                // thread bit or an outer qubit is +-sum_k p_k
-                if constexpr (NS == 2) {
-                    // per-thread sums in the state's precision, FP64 beyond
-                    using RT = typename RealOf<T>::type;
-                    RT S = 0, D[RB];
-#pragma unroll
-                    for (int j = 0; j < RB; j++) D[j] = 0;
-#pragma unroll
-                    for (int k = 0; k < R; k++) {
-                        const T f = v[0][k], m = v[1][k];
-                        const RT p = m.x * f.y - m.y * f.x;
-                        S += p;
-#pragma unroll
-                        for (int j = 0; j < RB; j++) D[j] += ((k >> j) & 1) ? -p : p;
-                    }
-                    const ReadZ* rz = reinterpret_cast<const ReadZ*>(phase + op.aux);
-                    const uint32_t utid = (uint32_t)tid;
-                    for (int e = 0; e < op.cnt; e++) {
-                        const int zj = rz[e].j, ztb = rz[e].tbit, zoa = rz[e].oa, zslot = rz[e].slot;
-                        RT pv;
-                        if (zj >= 0) {
-                            pv = D[0];
-#pragma unroll
-                            for (int j = 1; j < RB; j++) pv = zj == j ? D[j] : pv;
-                        } else {
-                            const bool bit = ztb >= 0 ? ((utid >> ztb) & 1u) != 0 : ((base >> zoa) & 1ull) != 0;
-                            pv = bit ? -S : S;
-                        }
-                        const double val = wave_total((double)pv);
-                        if (lane == 0) red[zslot * 8 + wave] = val;
-                    }
-                }
-                fresh_all<PP>(v, one);
-                break;
-            }
-#define F_G(J)                                                   \
-    if constexpr (NS == 2) {                                     \
-        double acc = reg_grad_xy<T, RB, J>(v, (double)mats[cur.mat].x, (double)mats[cur.mat].y); \
-        acc = wave_total(acc);                                     \
-        if (lane == 0) red[op.slot * 8 + wave] = acc;            \
-    }                                                            \
+#define F_G(J)                     \
+    read_body(v, cur, op);         \
     fresh_all<PP>(v, one)
                 QV_ALL1(RC_GXY, F_G)
 #undef F_G
@@ -812,19 +841,39 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         OpHot cur = op_hot(sop);
         if constexpr (PP) {
             T vb[NS][R];
-            for (int o = 0; o < nops; o += 2) {
+            int o = 0;
+            // a gradient read right after an op runs on the set that op wrote,
+            // instead of taking a turn of its own (which copies the state);
+            // a read that follows another read still takes a turn (letting up
+            // to three ride along measured no faster: more code per op)
+            auto read_after = [&](const T (&cs)[NS][R]) __attribute__((always_inline)) {
+                if constexpr (NS == 2) {
+                    if (o < nops && is_read_code(cur.code)) {
+                        const OpHot nxt = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+                        read_body(cs, cur, sop[o]);
+                        o++;
+                        cur = nxt;
+                    }
+                }
+            };
+            while (o < nops) {
                 const OpHot h1 = op_hot(sop + (o + 1 < nops ? o + 1 : o));
                 apply_op(v, vb, cur, sop[o]);
-                const OpHot h2 = op_hot(sop + (o + 2 < nops ? o + 2 : o));
-                if (o + 1 < nops) {
-                    apply_op(vb, v, h1, sop[o + 1]);
+                o++;
+                cur = h1;
+                read_after(vb);
+                if (o < nops) {
+                    const OpHot h2 = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+                    apply_op(vb, v, cur, sop[o]);
+                    o++;
+                    cur = h2;
+                    read_after(v);
                 } else {
 #pragma unroll
                     for (int s = 0; s < NS; s++)
 #pragma unroll
                         for (int k = 0; k < R; k++) v[s][k] = fresh(vb[s][k], one);
                 }
-                cur = h2;
             }
         } else {
             for (int o = 0; o < nops; o++) {
