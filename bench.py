@@ -108,6 +108,19 @@ def host_cpus() -> int:
         return os.cpu_count() or 1
 
 
+def gate_bytes(g, n, elem):
+    """Algorithmic HBM bytes of one unfused gate on an n-qubit state: a dense
+    one-qubit gate (and RZ, which phases both halves) or a general 4x4 reads
+    and writes every amplitude; CNOT and SWAP move half the state each way,
+    CZ and CP the |11> quarter."""
+    S = (1 << n) * elem
+    if g.op in ("cx", "swap"):
+        return S
+    if g.op in ("cz", "cp"):
+        return S / 2
+    return 2 * S
+
+
 def _oracle_rate(oracle, n, s, gates, budget):
     """Apply gates one by one to s until the time budget is crossed; return
     (gates done, seconds) around the gate loop only."""
@@ -139,10 +152,13 @@ def cpu_baseline(n: int, rand, x, qft, budget: float = 8.0):
     d_1, t_1 = _oracle_rate(oracle, n, s, rand, budget)
     oracle.set_threads(threads)
     del s
+    moved = sum(gate_bytes(g, n, 16) for g in rand[:d_r]) + sum(gate_bytes(g, n, 16) for g in qft[:d_q])
     return {
         "value": (d_r + d_q) / (t_r + t_q),
         "unit": "gate-applications/s",
         "cores": threads,
+        "effective_gbs": moved / (t_r + t_q) / 1e9,
+        "effective_gbs_1_thread": sum(gate_bytes(g, n, 16) for g in rand[:d_1]) / t_1 / 1e9,
         "kind": "oracle",
         "sample": f"{n}-qubit complex128 state: first {d_r} gates of the random U3 + CNOT circuit ({t_r:.1f} s) "
                   f"and first {d_q} gates of the QFT ({t_q:.1f} s) on {threads} threads; "
@@ -329,8 +345,9 @@ def c64_vs_c128(qv, n=33, depth=30):
     b = qv.State(n, torch.complex64)
     a.set_basis(0).apply(circ)
     b.set_basis(0).apply(circ)
-    t128, _ = timed(lambda: a.set_basis(0).apply(circ))
-    t64, _ = timed(lambda: b.set_basis(0).apply(circ))
+    # median of three timed runs each, after the warm run above
+    t128 = sorted(timed(lambda: a.set_basis(0).apply(circ))[0] for _ in range(3))[1]
+    t64 = sorted(timed(lambda: b.set_basis(0).apply(circ))[0] for _ in range(3))[1]
     d = a.compare(b)
     fid = (d["inner_re"] ** 2 + d["inner_im"] ** 2) / (d["norm2_a"] * d["norm2_b"])
     out = {"n_qubits": n, "gates": len(circ), "depth": depth,
@@ -575,6 +592,8 @@ def main() -> int:
         log("copy ...")
         out["copy"] = copy_rate(qv, B, n, dtype, elem, 5)
         out["sweeps"]["frac_of_copy_mean"] = sw["mean_gbs"] / out["copy"]["gbs"]
+        # the dominant kernel against the measured copy rate as well as the nominal peak
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy"]["gbs"]
         log("c64 vs c128 (33 qubits) ...")
         out["c64_vs_c128"] = c64_vs_c128(qv)
         log("adjoint (24-qubit ansatz) ...")
