@@ -103,8 +103,8 @@ def test_apply_matrix_with_controls(qv, dtype):
 # ------------------------------------------------------------ circuits ---
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n,n_gates,seed", [(3, 60, 0), (11, 200, 1), (12, 200, 2), (13, 300, 3),
-                                            (16, 400, 4), (19, 300, 5)])
+@pytest.mark.parametrize("n,n_gates,seed", [(3, 60, 0), (6, 100, 6), (8, 150, 7), (9, 150, 8), (10, 150, 9),
+                                            (11, 200, 1), (12, 200, 2), (13, 300, 3), (16, 400, 4), (19, 300, 5)])
 def test_random_mixed_circuits(qv, n, n_gates, seed, dtype):
     print(f"mixed n={n} gates={n_gates} seed={seed} dtype={dtype}", flush=True)
     circ = C.random_mixed_circuit(n, n_gates, seed)
@@ -423,6 +423,29 @@ def test_copy_kernel(qv):
     qv.copy(st, dst, src)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_degenerate_inputs(qv, dtype):
+    """An empty circuit leaves the state bit for bit (both paths); an empty
+    Pauli sum is 0; an adjoint call with no parameters returns the
+    expectation, an empty gradient and the circuit's input state."""
+    n = 13
+    psi0 = C.random_state(n, 3)
+    st = load(qv, n, psi0, dtype)
+    before = host(st)
+    st.apply([])
+    st.apply([], fused=False)
+    assert np.array_equal(host(st), before)
+    assert st.expect([]) == 0.0
+    circ = C.random_mixed_circuit(n, 60, 3)
+    H = C.zz_x_chain(n)
+    st.apply(circ)
+    f_want = st.expect(H)
+    f, g = st.adjoint_grad(circ, H, 0)
+    assert g.shape == (0,)
+    assert abs(f - f_want) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+    assert maxabs(host(st), before) <= TOL[dtype] * 10
 
 
 def test_bad_arguments_leave_state_untouched(qv):
