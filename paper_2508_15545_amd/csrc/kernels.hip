@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep1_plain(T* __restrict__ psi, 
     }
 }
 
-// Low targets without controls (2^k < 32): every lane loads one amplitude,
+// Low targets without controls (2^k <= 32): every lane loads one amplitude,
 // so each wave reads and writes whole contiguous runs, and takes the
 // partner amplitude i ^ 2^k from lane (lane ^ 2^k) of the same wave. Each
 // lane computes its own output row of Eq. 5.
@@ -271,15 +271,16 @@ hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
     if (g.ctrl != 0 && lane_gate(g, n)) return launch_gate_lane<T, 0>(psi, n, g, st);
     // Measured on MI355X at 29 qubits: one pair (or amplitude) per thread is
     // fastest while the partner stride is below 2^20 amplitudes (more,
-    // smaller workgroups walk memory more evenly: 6.8 TB/s for the lane
-    // form, about 6.1 for strides of 2^13..2^19 against 5.7 with 2 or 4
-    // pairs), 4 pairs once it is larger (about 5.65 TB/s either way).
+    // smaller workgroups walk memory more evenly: 6.7 TB/s for the lane
+    // form, which serves targets 0-5, about 6.1 for strides of 2^13..2^19
+    // against 5.7 with 2 or 4 pairs), 4 pairs once it is larger (about 5.65
+    // TB/s either way).
     const int k = g.q[0];
     const uint64_t mask = g.ctrl | (1ull << k);
     const Ins ins = make_ins(mask);
     const uint64_t npairs = 1ull << (n - ins.cnt);
     const T u00 = to_dev<T>(g.m[0]), u01 = to_dev<T>(g.m[1]), u10 = to_dev<T>(g.m[2]), u11 = to_dev<T>(g.m[3]);
-    if (g.ctrl == 0 && k < 3 && n >= 8) {
+    if (g.ctrl == 0 && k < 6 && n >= 8) {
         const uint64_t N = 1ull << n;
         with_per_thread(N, 1, [&](auto pc) {
             constexpr int P = decltype(pc)::value;
@@ -393,6 +394,62 @@ static bool is_swap_matrix(const HostGate& g)
     return true;
 }
 
+// A general 4x4 (no controls) on one qubit below 6 (ql) and one at 6 or
+// above (qh): each lane loads amplitude i (bit qh clear; the 64 lanes of a
+// wave hold 64 consecutive indices) and i | 2^qh, takes the ql-partners of
+// both by lane shuffles and writes its own two rows, so that every load and
+// store instruction of a wave covers a whole contiguous kilobyte (complex128)
+// where the quadruple sweep would touch half of each 128-byte line per
+// instruction. qa / qc keep the gate's own order: index bit(qa) + 2 bit(qc).
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_sweep2_lane(T* __restrict__ psi, uint64_t nhalf, int ql, int qh,
+                                                          bool low_is_a, Mat4 m)
+{
+    using R = typename RealOf<T>::type;
+    auto U = [&](int e) {
+        T u;
+        u.x = (R)m.v[2 * e];
+        u.y = (R)m.v[2 * e + 1];
+        return u;
+    };
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t hb = 1ull << qh, lo = hb - 1;
+    const int bl = (int)((threadIdx.x >> ql) & 1);  // bit ql of the index (kThreads is a multiple of 64)
+    // quadruple index of (bit ql, bit qh) in the gate's order
+    auto idx = [&](int l, int h) { return low_is_a ? l + 2 * h : h + 2 * l; };
+    T v0[P] = {}, v1[P] = {};
+    uint64_t i0[P];
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        i0[r] = ((p & ~lo) << 1) | (p & lo);
+        if (p < nhalf) {
+            v0[r] = ld_nt(psi + i0[r]);
+            v1[r] = ld_nt(psi + (i0[r] | hb));
+        }
+    }
+    const int r0 = idx(bl, 0), r1 = idx(bl, 1);  // this lane's two output rows
+    const int c_own0 = idx(bl, 0), c_own1 = idx(bl, 1), c_par0 = idx(bl ^ 1, 0), c_par1 = idx(bl ^ 1, 1);
+#pragma unroll
+    for (int r = 0; r < P; r++) {
+        const uint64_t p = base + (uint64_t)r * kThreads;
+        const T p0 = shfl_xor_amp(v0[r], 1 << ql), p1 = shfl_xor_amp(v1[r], 1 << ql);  // every lane shuffles
+        const T a0 = cmul2(U(4 * r0 + c_own0), v0[r], U(4 * r0 + c_par0), p0);
+        const T b0 = cmul2(U(4 * r0 + c_own1), v1[r], U(4 * r0 + c_par1), p1);
+        const T a1 = cmul2(U(4 * r1 + c_own0), v0[r], U(4 * r1 + c_par0), p0);
+        const T b1 = cmul2(U(4 * r1 + c_own1), v1[r], U(4 * r1 + c_par1), p1);
+        T o0, o1;
+        o0.x = a0.x + b0.x;
+        o0.y = a0.y + b0.y;
+        o1.x = a1.x + b1.x;
+        o1.y = a1.y + b1.y;
+        if (p < nhalf) {
+            st_nt(psi + i0[r], o0);
+            st_nt(psi + (i0[r] | hb), o1);
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
 {
@@ -414,6 +471,16 @@ hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
     for (int e = 0; e < 16; e++) {
         m.v[2 * e] = g.m[e].real();
         m.v[2 * e + 1] = g.m[e].imag();
+    }
+    const int qlo = g.q[0] < g.q[1] ? g.q[0] : g.q[1], qhi = g.q[0] < g.q[1] ? g.q[1] : g.q[0];
+    if (g.ctrl == 0 && qlo < 6 && qhi >= 6 && n >= 8) {
+        const uint64_t nhalf = 1ull << (n - 1);
+        with_per_thread(nhalf, 1, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL((k_sweep2_lane<T, P>), dim3(grid_for(nhalf, kThreads * P)), dim3(kThreads), 0, st,
+                               psi, nhalf, qlo, qhi, g.q[0] == qlo, m);
+        });
+        return hipGetLastError();
     }
     with_per_thread(nquads, 2, [&](auto pc) {
         constexpr int P = decltype(pc)::value;

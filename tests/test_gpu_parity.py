@@ -563,7 +563,8 @@ def test_low_qubit_sweeps(qv, dtype):
     """Unfused gates whose qubits all lie among the lowest five (one
     coalesced lane pass): every two-qubit op on every ordered pair of
     qubits 0..4, one-qubit matrices with one and two low controls, and a
-    controlled one-qubit gate mixing low and high qubits."""
+    controlled one-qubit gate mixing low and high qubits; one-qubit gates on
+    targets 0..5 and 4x4 gates on a low and a high qubit (lane shuffles)."""
     n = 10
     rng = C.rng_for(77)
     psi = C.random_state(n, 12)
@@ -577,6 +578,13 @@ def test_low_qubit_sweeps(qv, dtype):
             gates.append(C.gate("cp", a, b, params=(1.1,)))
             gates.append(C.gate("swap", a, b))
             gates.append(C.gate("mat2", a, b, params=C.matrix_params(C.random_unitary(4, rng))))
+    # one-qubit gates on targets 0..5 (lane shuffles within a wave), and 4x4
+    # gates on one qubit below 6 and one above (lanes plus a strided half)
+    for t in range(6):
+        gates.append(C.gate("u3", t, params=tuple(rng.uniform(0, 2 * math.pi, 3))))
+        gates.append(C.gate("mat1", t, params=C.matrix_params(C.random_unitary(2, rng))))
+    for a, b in [(3, 7), (8, 5), (0, 9), (9, 2), (5, 6)]:
+        gates.append(C.gate("mat2", a, b, params=C.matrix_params(C.random_unitary(4, rng))))
     want = psi.copy()
     for g in gates:
         want = oracle.apply_gate(want, n, g)
