@@ -482,7 +482,9 @@ hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
         });
         return hipGetLastError();
     }
-    with_per_thread(nquads, 2, [&](auto pc) {
+    // 4 quadruples per thread when both qubits are 11 or above (measured 2-3%
+    // faster there at 29 qubits), 2 otherwise
+    with_per_thread(nquads, qlo >= 11 ? 4 : 2, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
         hipLaunchKernelGGL((k_sweep2<T, P>), dim3(grid_for(nquads, kThreads * P)), dim3(kThreads), 0, st, psi,
                            nquads, g.q[0], g.q[1], ins, g.ctrl, m);
