@@ -428,15 +428,16 @@ __device__ __forceinline__ double reg_grad_xy(const T (&v)[2][1 << RB], double c
 // target drops to three waves per SIMD.
 // The single-state complex128 kernel with r = 4 is held to 168 VGPRs, three
 // waves per SIMD, which its half-size exchange buffer lets the LDS hold; the
-// single-state complex64 one to 96 VGPRs, five waves per SIMD, as many as
-// its 32 KiB exchange buffers let a CU's LDS hold.
+// single-state complex64 one to 128 VGPRs, four waves per SIMD (its two
+// register sets need more than the 96 of five; two sets at four waves
+// measured 2% faster than one set at five).
 template <typename T, int RB, int NS, bool PF, bool MF = false>
 constexpr int block_waves_per_eu()
 {
     return MF ? 4
          : (RB == 3 && NS == 1) ? (PF ? 3 : 4)
          : (split_exchange<T, NS>() && !PF) ? 3
-         : (sizeof(T) == 8 && NS == 1 && !PF) ? 5 : 1;
+         : (sizeof(T) == 8 && NS == 1 && !PF) ? 4 : 1;
 }
 
 // MF: the variant whose plans may hold matrix-core 4x4 ops (RC_D2M); a kernel
@@ -458,8 +459,10 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
     const int b = hdr->b;
     const int nloc = 1 << b;
     const int tb = b - RB;
-    // two register sets in the op loop (see there)
-    constexpr bool PP = sizeof(T) == 16 || NS == 2;
+    // two register sets in the op loop (see there); the one-set loop stays
+    // for comparison (measured 2% slower for complex64 at five waves per SIMD
+    // than two sets at four)
+    constexpr bool PP = true;
     // 1.0, read at run time (see fresh)
     const typename RealOf<T>::type one = (typename RealOf<T>::type)(hdr->pad + 1);
     const int tid = threadIdx.x;
@@ -561,8 +564,6 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         // v = op(vb)): each op writes its results into the other set, so a
         // dense update is not copied back into the registers it read before
         // the next op (with one set, every op ends in a copy of the state).
-        // The complex64 single-state kernel keeps one set: the second would
-        // cost it registers below its five waves per SIMD.
         // Gradient reads (Im <lambda|G|phi> into the wave's LDS slots) leave
         // the state as it is; with two register sets they run on whichever
         // set holds the state, between the ops that change it.
@@ -839,7 +840,24 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
         // so that each op waits for one round of scalar loads (its matrix)
         // instead of three.
         OpHot cur = op_hot(sop);
-        if constexpr (PP) {
+        if constexpr (PP && NS == 1) {
+            // no reads: ops in pairs, the second of an odd tail a copy
+            T vb[NS][R];
+            for (int o = 0; o < nops; o += 2) {
+                const OpHot h1 = op_hot(sop + (o + 1 < nops ? o + 1 : o));
+                apply_op(v, vb, cur, sop[o]);
+                const OpHot h2 = op_hot(sop + (o + 2 < nops ? o + 2 : o));
+                if (o + 1 < nops) {
+                    apply_op(vb, v, h1, sop[o + 1]);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < NS; s++)
+#pragma unroll
+                        for (int k = 0; k < R; k++) v[s][k] = fresh(vb[s][k], one);
+                }
+                cur = h2;
+            }
+        } else if constexpr (PP) {
             T vb[NS][R];
             int o = 0;
             // a gradient read right after an op runs on the set that op wrote,
