@@ -75,11 +75,26 @@ hipError_t launch_init_basis(T* psi, int n, uint64_t x, hipStream_t st)
 // bits set. Each thread owns P pairs spaced kThreads apart so that each
 // wave's loads are contiguous runs; all 2P loads are issued before any math.
 
+// Workgroup index with the XCD index moved: workgroups are dispatched
+// round-robin over the eight XCDs, so the low three bits of blockIdx.x name
+// the XCD; with sb >= 0 they become bits sb..sb+2 of the index (the grid is
+// a multiple of 2^(sb+3) then), and each XCD sweeps runs of 2^sb
+// consecutive workgroups. sb < 0 keeps the dispatch order.
+__device__ __forceinline__ uint64_t xcd_block(int sb)
+{
+    uint64_t blk = blockIdx.x;
+    if (sb >= 0) {
+        const uint64_t j = blk & 7, r = blk >> 3;
+        blk = ((r >> sb) << (sb + 3)) | (j << sb) | (r & ((1ull << sb) - 1));
+    }
+    return blk;
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_sweep1(T* __restrict__ psi, uint64_t npairs, int k, Ins ins,
-                                                     uint64_t ctrl, T u00, T u01, T u10, T u11)
+                                                     uint64_t ctrl, T u00, T u01, T u10, T u11, int sb)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t base = xcd_block(sb) * (kThreads * P) + threadIdx.x;
     const uint64_t kb = 1ull << k;
     T x[P], y[P];
     uint64_t i0[P];
@@ -108,9 +123,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep1(T* __restrict__ psi, uint64
 // shift and a mask instead of the general insertion.
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_sweep1_plain(T* __restrict__ psi, uint64_t npairs, int k, T u00,
-                                                           T u01, T u10, T u11)
+                                                           T u01, T u10, T u11, int sb)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t base = xcd_block(sb) * (kThreads * P) + threadIdx.x;
     const uint64_t kb = 1ull << k, lo = kb - 1;
     T x[P], y[P];
     uint64_t i0[P];
@@ -265,21 +280,51 @@ static hipError_t launch_gate_lane(T* psi, int n, const HostGate& g, hipStream_t
     return hipGetLastError();
 }
 
+// Index bit that takes the XCD index (xcd_block) in a one-qubit sweep on
+// target k, controlled or not (mask: the target and control bits), from
+// sweeps of every split bit against every target and several control /
+// target pairs at 29 qubits on MI355X, complex128 and complex64. A partner
+// 8 MiB or more away (partner byte bit X >= 23) runs best with the split on
+// amplitude byte bit 17 + (X mod 4): 6.0-6.5 TB/s, where the dispatch order
+// gives 5.5-5.9 and a split chosen without regard to X drops to 5.2-5.7 for
+// one X in two. Other partners, and a control on that bit, take index bit
+// 15 (6.1-6.7 TB/s), or 16 at X = 20 (6.19 against 5.94 TB/s).
+static int sweep_xcd_bit(int k, uint64_t mask, size_t elem)
+{
+    const int eb = elem == 16 ? 4 : 3;  // log2 of the amplitude's bytes
+    const int X = k + eb;
+    if (X >= 23) {
+        const int A = 17 + (X & 3) - eb;  // amplitude bit
+        if (!((mask >> A) & 1)) return A - __builtin_popcountll(mask & ((1ull << A) - 1));
+    }
+    return X == 20 ? 16 : 15;
+}
+
+// xcd_block's sb for index bit `bit` with P items per thread, or -1 where the
+// grid is too small to be cut that way.
+static int xcd_shift(int bit, int P, unsigned grid)
+{
+    const int sb = bit - 8 - __builtin_ctz(P);
+    return (sb < 0 || grid % (8u << sb) != 0) ? -1 : sb;
+}
+
 template <typename T>
 hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
 {
     if (g.ctrl != 0 && lane_gate(g, n)) return launch_gate_lane<T, 0>(psi, n, g, st);
-    // Measured on MI355X at 29 qubits: one pair (or amplitude) per thread is
-    // fastest while the partner stride is below 2^20 amplitudes (more,
-    // smaller workgroups walk memory more evenly: 6.7 TB/s for the lane
-    // form, which serves targets 0-5, about 6.1 for strides of 2^13..2^19
-    // against 5.7 with 2 or 4 pairs), 4 pairs once it is larger (about 5.65
-    // TB/s either way).
+    // Measured on MI355X at 29 qubits: one amplitude per lane with the
+    // partner taken by a lane shuffle for targets 0-5 (6.75 TB/s); one pair
+    // per thread above, with the eight XCDs' share of the workgroups placed
+    // by sweep_xcd_bit (6.0-6.7 TB/s against 5.6-5.85 with the dispatch
+    // order and one or four pairs per thread). Without such a split (small
+    // grids), four pairs per thread once the partner stride reaches 2^20.
     const int k = g.q[0];
     const uint64_t mask = g.ctrl | (1ull << k);
     const Ins ins = make_ins(mask);
     const uint64_t npairs = 1ull << (n - ins.cnt);
     const T u00 = to_dev<T>(g.m[0]), u01 = to_dev<T>(g.m[1]), u10 = to_dev<T>(g.m[2]), u11 = to_dev<T>(g.m[3]);
+    const int bit = sweep_xcd_bit(k, mask, sizeof(T));
+    const bool split = xcd_shift(bit, 1, grid_for(npairs, kThreads)) >= 0;
     if (g.ctrl == 0 && k < 6 && n >= 8) {
         const uint64_t N = 1ull << n;
         with_per_thread(N, 1, [&](auto pc) {
@@ -288,16 +333,18 @@ hipError_t launch_sweep1(T* psi, int n, const HostGate& g, hipStream_t st)
                                N, k, u00, u01, u10, u11);
         });
     } else if (g.ctrl == 0) {
-        with_per_thread(npairs, k < 20 ? 1 : 4, [&](auto pc) {
+        with_per_thread(npairs, split || k < 20 ? 1 : 4, [&](auto pc) {
             constexpr int P = decltype(pc)::value;
-            hipLaunchKernelGGL((k_sweep1_plain<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st,
-                               psi, npairs, k, u00, u01, u10, u11);
+            const unsigned grid = grid_for(npairs, kThreads * P);
+            hipLaunchKernelGGL((k_sweep1_plain<T, P>), dim3(grid), dim3(kThreads), 0, st, psi, npairs, k, u00, u01,
+                               u10, u11, xcd_shift(bit, P, grid));
         });
     } else {
-        with_per_thread(npairs, k < 20 ? 1 : 4, [&](auto pc) {
+        with_per_thread(npairs, split || k < 20 ? 1 : 4, [&](auto pc) {
             constexpr int P = decltype(pc)::value;
-            hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st, psi,
-                               npairs, k, ins, g.ctrl, u00, u01, u10, u11);
+            const unsigned grid = grid_for(npairs, kThreads * P);
+            hipLaunchKernelGGL((k_sweep1<T, P>), dim3(grid), dim3(kThreads), 0, st, psi, npairs, k, ins, g.ctrl,
+                               u00, u01, u10, u11, xcd_shift(bit, P, grid));
         });
     }
     return hipGetLastError();

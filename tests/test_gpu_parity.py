@@ -559,6 +559,32 @@ def test_complex64_matrix_core_4x4(qv, monkeypatch, kind, n, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_sweeps_with_xcd_split(qv, dtype):
+    """Unfused one-qubit gates on every target of a 22-qubit state: from 19
+    qubits up the sweep places each XCD's workgroups by a split bit that
+    depends on the target and the amplitude size, so every target (near
+    and far partners, both split rules) is checked against the oracle."""
+    n = 22
+    print(f"xcd-split sweeps n={n} dtype={dtype}", flush=True)
+    rng = C.rng_for(22)
+    psi = C.random_state(n, 22)
+    gates = [C.gate("mat1", t, params=C.matrix_params(C.random_unitary(2, rng))) for t in range(n)]
+    # controlled sweeps: controls below, on and above the split bit
+    for a, b in [(11, 20), (20, 11), (13, 21), (13, 20), (14, 20), (3, 19), (21, 0), (17, 16)]:
+        gates.append(C.gate("cx", a, b))
+    want = psi.copy()
+    for g in gates:
+        want = oracle.apply_gate(want, n, g)
+    st = load(qv, n, psi, dtype)
+    st.apply(gates, fused=False)
+    for (t, ctrls) in [(21, (13, 14)), (20, (0, 16)), (16, (15, 21))]:
+        u = C.random_unitary(2, rng)
+        st.apply_matrix([t], u, controls=ctrls)
+        want = oracle.apply_1q(want, n, t, u, ctrl_mask=sum(1 << c for c in ctrls))
+    assert maxabs(host(st), want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_low_qubit_sweeps(qv, dtype):
     """Unfused gates whose qubits all lie among the lowest five (one
     coalesced lane pass): every two-qubit op on every ordered pair of
