@@ -178,7 +178,12 @@ sv_status sv_apply_unfused(sv_state s, const sv_gate* gates, int n_gates);
  * each one HBM round trip of the state (Sec. III.C block storage, Sec. III.E
  * one traversal for a batch of gates); diagonal gates join any pass. The
  * result equals applying the gates one by one in order (up to rounding).
- * Errors: SV_EINVAL for a bad op, qubit, control or reserved field. */
+ * On states of 1 GiB and more each pass is launched as soon as it is planned
+ * (QVEC_STREAM_PLAN=0 / 1 turns that off / on at any size).
+ * Errors: SV_EINVAL for a bad op, qubit, control or reserved field (the
+ * state is unchanged); SV_EINVAL from the planner itself, which valid input
+ * does not produce, may come after passes planned before it were applied
+ * (its message says so). */
 sv_status sv_apply_fused(sv_state s, const sv_gate* gates, int n_gates);
 
 /* Plan statistics for sv_apply_fused of this circuit on an n-qubit state

@@ -425,6 +425,90 @@ sv_status run_plan(sv_state s, const std::vector<PlanPass>& passes, T* s0, T* s1
     return SV_OK;
 }
 
+// One pass of a streamed plan (sv_apply_fused on large states): the
+// pass's tables go to the next free region of the pinned staging buffer and
+// of the device table (from *cursor), are copied on the state's stream and
+// the pass is launched at once, so that the host plans the next pass while
+// this one runs. A region is never rewritten while a copy from it may be
+// pending: the caller starts at 0 only after the previous call's last copy
+// (table_done), and a pass that does not fit waits for the stream before the
+// buffers grow and the cursor goes back to 0.
+template <typename T>
+sv_status run_pass_streamed(sv_state s, const PlanPass& pp, T* psi, size_t* cursor)
+{
+    if (pp.kind != PlanPass::BLOCK) {
+        if (pp.kind == PlanPass::SWEEP1) {
+            LaunchTimer tm(s, KF_SWEEP1);
+            HIP_TRY(launch_sweep1<T>(psi, s->n, pp.gate, s->stream));
+        } else if (pp.kind == PlanPass::SWEEP2) {
+            LaunchTimer tm(s, KF_SWEEP2);
+            HIP_TRY(launch_sweep2<T>(psi, s->n, pp.gate, s->stream));
+        } else {
+            LaunchTimer tm(s, KF_DIAG);
+            HIP_TRY(launch_sweep_diag<T>(psi, s->n, pp.gate, s->stream));
+        }
+        return SV_OK;
+    }
+    const size_t o_st = align_up(sizeof(PassHdr), 256);
+    const size_t o_ops = align_up(o_st + pp.stages.size() * sizeof(StageHdr), 256);
+    const size_t o_mats = align_up(o_ops + pp.ops.size() * sizeof(TileOp), 256);
+    const size_t o_ph = align_up(o_mats + pp.mats.size() * sizeof(T), 256);
+    const size_t size = align_up(o_ph + pp.phase.size() * sizeof(PhaseTerm), 256);
+    if (*cursor + size > s->h_table_cap || *cursor + size > s->d_table_cap) {
+        HIP_TRY(hipStreamSynchronize(s->stream));  // nothing reads either buffer after this
+        s->table_pending = false;
+        *cursor = 0;
+        const size_t want = std::max<size_t>(size * 64, (size_t)1 << 20);
+        if (s->h_table_cap < want) {
+            if (s->h_table) HIP_TRY(hipHostFree(s->h_table));
+            s->h_table = nullptr;
+            s->h_table_cap = 0;
+            if (hipHostMalloc((void**)&s->h_table, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(SV_ENOMEM, "pinned host allocation failed");
+            }
+            s->h_table_cap = want;
+        }
+        sv_status st = ensure_device(&s->d_table, &s->d_table_cap, want, s->stream);
+        if (st != SV_OK) return st;
+    }
+    unsigned char* h = s->h_table + *cursor;
+    PassHdr hdr = pp.hdr;
+    hdr.op_begin = 0;
+    hdr.stage_begin = 0;
+    hdr.n_stages = (int32_t)pp.stages.size();
+    std::memcpy(h, &hdr, sizeof(hdr));
+    StageHdr* S = reinterpret_cast<StageHdr*>(h + o_st);
+    for (size_t i = 0; i < pp.stages.size(); i++) S[i] = pp.stages[i];
+    TileOp* O = reinterpret_cast<TileOp*>(h + o_ops);
+    for (size_t i = 0; i < pp.ops.size(); i++) O[i] = pp.ops[i];
+    T* M = reinterpret_cast<T*>(h + o_mats);
+    for (size_t i = 0; i < pp.mats.size(); i++) {
+        using R = std::remove_reference_t<decltype(M[0].x)>;
+        M[i].x = (R)pp.mats[i].real();
+        M[i].y = (R)pp.mats[i].imag();
+    }
+    PhaseTerm* P = reinterpret_cast<PhaseTerm*>(h + o_ph);
+    for (size_t i = 0; i < pp.phase.size(); i++) P[i] = pp.phase[i];
+    unsigned char* d = static_cast<unsigned char*>(s->d_table) + *cursor;
+    HIP_TRY(hipMemcpyAsync(d, h, size, hipMemcpyHostToDevice, s->stream));
+    *cursor += size;
+    const int b = pp.hdr.b;
+    const int64_t nblocks = (int64_t)1 << (s->n - b);
+    LaunchTimer tm(s, KF_BLOCK);
+    const PassHdr* d_hdr = reinterpret_cast<const PassHdr*>(d);
+    if (pp.reg_bits > 0) {
+        HIP_TRY((launch_block_reg<T>(psi, nullptr, s->n, 1, pp.reg_bits, d_hdr,
+                                     reinterpret_cast<const StageHdr*>(d + o_st),
+                                     reinterpret_cast<const TileOp*>(d + o_ops), reinterpret_cast<const T*>(d + o_mats),
+                                     reinterpret_cast<const PhaseTerm*>(d + o_ph), b, s->d_part, nblocks, s->stream)));
+    } else {
+        HIP_TRY((launch_block_pass<T>(psi, nullptr, s->n, 1, d_hdr, reinterpret_cast<const TileOp*>(d + o_ops),
+                                      reinterpret_cast<const T*>(d + o_mats), b, s->d_part, nblocks, s->stream)));
+    }
+    return SV_OK;
+}
+
 template <typename F>
 sv_status dispatch(sv_state s, F&& f)
 {
@@ -478,6 +562,18 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
         while (o.b - o.reg_bits > 9) o.b--;
     } else {
         o.b = std::min(o.b, (elem == 16 ? 12 : 13) - (n_states == 2 ? 1 : 0));
+    }
+    // Lookahead in each pass's choice of local qubits (fewer passes for more
+    // host time: about 1 ms per pass with 8 candidates) on states of 4 GiB
+    // and more, where a pass takes milliseconds on the GPU and
+    // sv_apply_fused plans each pass while the previous one runs.
+    // QVEC_LOOKAHEAD=<k> sets the candidates (0: off).
+    const uint64_t state_bytes = ((uint64_t)1 << n) * (uint64_t)elem * (uint64_t)n_states;
+    o.lookahead_sets = (n_states == 1 && state_bytes >= (4ull << 30)) ? 8 : 0;
+    const char* la = std::getenv("QVEC_LOOKAHEAD");
+    if (la) {
+        const int v = std::atoi(la);
+        if (v >= 0 && v <= 64) o.lookahead_sets = v;
     }
     return o;
 }
@@ -775,9 +871,43 @@ sv_status sv_apply_fused(sv_state s, const sv_gate* gates, int n_gates)
     if (st != SV_OK) return st;
     if (hg.empty()) return SV_OK;
     DeviceGuard dg(s->device);
+    const PlanOptions opt = plan_options(s->n, s->elem, 1);
+    // States of 1 GiB and more (a pass takes half a millisecond or more on
+    // the GPU): each pass is launched as soon as it is planned.
+    // QVEC_STREAM_PLAN=0 / 1 turns this off / on at any size.
+    const char* sp = std::getenv("QVEC_STREAM_PLAN");
+    const bool stream = sp ? std::strcmp(sp, "1") == 0 : (((uint64_t)1 << s->n) * s->elem >= (1ull << 30));
+    if (stream) {
+        return dispatch(s, [&](auto* psi) -> sv_status {
+            using T = std::remove_pointer_t<decltype(psi)>;
+            if (s->table_pending) {  // the staging buffer may still feed the last call's copy
+                HIP_TRY(hipEventSynchronize(s->table_done));
+                s->table_pending = false;
+            }
+            size_t cursor = 0;
+            sv_status st = SV_OK;
+            bool any = false;
+            try {
+                plan_circuit_stream(s->n, forward_items(hg), opt, (int)s->elem, [&](PlanPass&& pp) {
+                    st = run_pass_streamed<T>(s, pp, psi, &cursor);
+                    any = true;
+                    return st == SV_OK;
+                });
+            } catch (const std::exception& e) {
+                (void)hipStreamSynchronize(s->stream);
+                return fail(SV_EINVAL, std::string("planner: ") + e.what() +
+                                           (any ? " (the passes planned before it were applied)" : ""));
+            }
+            if (any) {
+                HIP_TRY(hipEventRecord(s->table_done, s->stream));
+                s->table_pending = true;
+            }
+            return st;
+        });
+    }
     std::vector<PlanPass> passes;
     try {
-        passes = plan_circuit(s->n, forward_items(hg), plan_options(s->n, s->elem, 1), (int)s->elem);
+        passes = plan_circuit(s->n, forward_items(hg), opt, (int)s->elem);
     } catch (const std::exception& e) {
         return fail(SV_EINVAL, std::string("planner: ") + e.what());
     }

@@ -18,6 +18,7 @@
 // So the pass result equals applying the gates one by one (Sec. III.E: one
 // traversal for a batch of gates, same result as gate by gate).
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -1079,7 +1080,8 @@ void check_mappings(const PlanPass& pp, int r, const int32_t* store_q)
     }
 }
 
-std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in, const PlanOptions& opt, int elem)
+void plan_circuit_stream(int n, const std::vector<PlanItem>& items_in, const PlanOptions& opt, int elem,
+                         const std::function<bool(PlanPass&&)>& emit)
 {
     if (n < 1 || n > kMaxQubits) throw std::runtime_error("qubit count out of range");
     const int b = std::min(opt.b, n);
@@ -1109,7 +1111,6 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
     for (size_t i = 0; i < items.size(); i++) ib[i] = bits_of(items[i]);
 
     std::vector<char> done(items.size(), 0);
-    std::vector<PlanPass> passes;
     const int coal = (b == n) ? 0 : std::min(opt.coalesce, b);
     const bool staged = opt.reg_bits > 0 && b - opt.reg_bits >= 6 && b - opt.reg_bits <= 9;
     // Qubit moves: items keep their own (logical) qubit numbers; logical qubit
@@ -1172,18 +1173,21 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
     // second choice, from the first pending item's qubits, add one candidate
     // item's missing qubits at a time, the ones that let the most further
     // items in per added qubit. Keeps whichever set takes more items.
-    auto choose = [&](size_t first, uint64_t S0, std::vector<size_t>& taken) {
+    // skip_first: in the first growth step, pass over the skip_first best
+    // additions (a different start for the lookahead's candidates).
+    auto choose = [&](size_t first, uint64_t S0, std::vector<size_t>& taken, int skip_first = 0,
+                      bool greedy = true) {
         uint64_t S = S0;
         taken.clear();
-        scan(first, S, true, &taken);
+        if (greedy) scan(first, S, true, &taken);
         if (opt.best_gain && b < n) {
             uint64_t S1 = S0 | ib[first].dense;
             if (popc(S1) <= b) {
+                int step = 0;
                 while (true) {
                     uint64_t t = S1;
                     const int base = scan(first, t, false, nullptr);
-                    double best = 0;
-                    uint64_t best_S = 0;
+                    std::vector<std::pair<double, uint64_t>> cand;
                     int seen = 0;
                     for (size_t i = first; i < items.size() && seen < opt.gain_candidates; i++) {
                         if (done[i]) continue;
@@ -1192,21 +1196,68 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                         if (!need || popc(S1 | need) > b) continue;
                         uint64_t u = S1 | need;
                         const double gain = (double)(scan(first, u, false, nullptr) - base) / popc(need);
-                        if (gain > best) {
-                            best = gain;
-                            best_S = S1 | need;
-                        }
+                        if (gain > 0) cand.push_back({gain, S1 | need});
                     }
-                    if (best <= 0) break;
-                    S1 = best_S;
+                    // best gain first; equal gains keep item order
+                    std::stable_sort(cand.begin(), cand.end(),
+                                     [](const std::pair<double, uint64_t>& x, const std::pair<double, uint64_t>& y) {
+                                         return x.first > y.first;
+                                     });
+                    // distinct sets only
+                    cand.erase(std::unique(cand.begin(), cand.end(),
+                                           [](const std::pair<double, uint64_t>& x,
+                                              const std::pair<double, uint64_t>& y) { return x.second == y.second; }),
+                               cand.end());
+                    const size_t pick = step == 0 ? (size_t)skip_first : 0;
+                    if (pick >= cand.size()) break;
+                    S1 = cand[pick].second;
+                    step++;
                 }
+                if (skip_first > 0 && step == 0) return (uint64_t)0;  // no such start
                 std::vector<size_t> taken1;
                 uint64_t u = S1;
                 scan(first, u, false, &taken1);
-                if (taken1.size() >= taken.size()) {
+                if (!greedy || taken1.size() >= taken.size()) {
                     taken.swap(taken1);
                     S = S1;
                 }
+            }
+        }
+        return S;
+    };
+    // With lookahead_sets > 0: more candidate local sets (best-gain growths
+    // whose first step takes the 1st, 2nd, ... best addition instead of the
+    // best), each scored by the items it takes plus the items the following
+    // pass would take after it (chosen without lookahead); the best score
+    // wins, ties going to the set that takes more now. On the 29-qubit random
+    // U3 + CNOT circuit of depth 40 this plans 39 passes instead of 43 (8
+    // candidates), at about 1 ms of host time per pass.
+    auto choose_la = [&](size_t first, uint64_t S0, std::vector<size_t>& taken) {
+        uint64_t S = choose(first, S0, taken);
+        if (opt.lookahead_sets <= 0 || b >= n) return S;
+        auto next_count = [&](const std::vector<size_t>& tk) {
+            for (size_t i : tk) done[i] = 1;
+            size_t f = first;
+            while (f < items.size() && done[f]) f++;
+            size_t c = 0;
+            if (f < items.size()) {
+                std::vector<size_t> t2;
+                choose(f, S0, t2);
+                c = t2.size();
+            }
+            for (size_t i : tk) done[i] = 0;
+            return c;
+        };
+        size_t best = taken.size() + next_count(taken);
+        for (int v = 0; v <= opt.lookahead_sets; v++) {
+            std::vector<size_t> tk;
+            const uint64_t Sv = choose(first, S0, tk, v, false);
+            if (!Sv || tk.empty()) continue;
+            const size_t sc = tk.size() + next_count(tk);
+            if (sc > best || (sc == best && tk.size() > taken.size())) {
+                best = sc;
+                taken.swap(tk);
+                S = Sv;
             }
         }
         return S;
@@ -1224,7 +1275,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             for (int q = 0; q < coal; q++) S0 |= 1ull << logi[q];
         }
         std::vector<size_t> taken;
-        uint64_t S = choose(first, S0, taken);
+        uint64_t S = choose_la(first, S0, taken);
         if (taken.empty()) throw std::runtime_error("planner made no progress");
         // fill with qubits away from their own bit (so that they can go back),
         // then with the lowest qubits
@@ -1248,7 +1299,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
                                                                                 : PlanPass::SWEEPDIAG;
             pp.gate = pp.kind == PlanPass::SWEEPDIAG ? sweep_form(g) : g;
             pp.bytes = sweep_bytes(pp.gate, n, elem);
-            passes.push_back(pp);
+            if (!emit(std::move(pp))) return;
             continue;
         }
 
@@ -1442,7 +1493,7 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
             check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);
         }
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
-        passes.push_back(std::move(pp));
+        if (!emit(std::move(pp))) return;
     }
     // Qubits still away from their own bit: passes with no gates that move
     // them back, a few pairs (qubit, holder of its bit) at a time.
@@ -1519,8 +1570,17 @@ std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items_in,
         set_io_offsets(pp.hdr, opt.reg_bits, store_q);
         check_mappings(pp, opt.reg_bits, store_q);
         pp.bytes = 2.0 * n_states * std::ldexp(1.0, n) * elem;
-        passes.push_back(std::move(pp));
+        if (!emit(std::move(pp))) return;
     }
+}
+
+std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, const PlanOptions& opt, int elem)
+{
+    std::vector<PlanPass> passes;
+    plan_circuit_stream(n, items, opt, elem, [&](PlanPass&& pp) {
+        passes.push_back(std::move(pp));
+        return true;
+    });
     return passes;
 }
 

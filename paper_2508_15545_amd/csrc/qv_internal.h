@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -244,6 +245,7 @@ struct PlanOptions {
     int lookahead = 4096;  // gates scanned when filling a pass
     bool best_gain = true;     // also try growing each pass's local set by best gain per qubit
     int gain_candidates = 64;  // pending items tried as additions per growth step
+    int lookahead_sets = 0;    // extra candidate local sets scored with the next pass (0: off)
     bool single_gate_sweeps = true;  // a pass holding one gate uses its sweep kernel
     int reg_bits = 0;      // register-window bits r (0: no stage planning)
     bool merge_diagonals = true;  // runs of diagonal gates become phase polynomials
@@ -274,6 +276,12 @@ struct PlanItem {
 
 std::vector<PlanPass> plan_circuit(int n, const std::vector<PlanItem>& items, const PlanOptions& opt,
                                    int elem_bytes);
+
+// The same plan, each pass handed to `emit` as soon as it is complete, in
+// order (a pass is not changed after that, so it can run while the next one
+// is planned); emit returns false to stop planning.
+void plan_circuit_stream(int n, const std::vector<PlanItem>& items, const PlanOptions& opt, int elem_bytes,
+                         const std::function<bool(PlanPass&&)>& emit);
 
 // Block size in local qubits for a state of n qubits.
 int default_block_qubits(int n, int elem_bytes, int n_states);

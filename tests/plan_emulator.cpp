@@ -311,6 +311,7 @@ int main(int argc, char** argv)
     g_slot_bytes = o.lds_elem;
     o.prefuse = true;
     o.park = std::atoi(argv[3]) > 0;
+    if (argc > 5) o.lookahead_sets = std::atoi(argv[5]);  // candidate local sets scored with the next pass
     const std::vector<PlanPass> passes = plan_circuit(n, items, o, elem);
     const int bad = check_structure(passes);
     std::vector<C> psi(1ull << n), ref;

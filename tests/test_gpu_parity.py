@@ -163,7 +163,8 @@ def test_qubit_moves_between_passes(qv, monkeypatch, kind, n, seed, dtype):
 KNOBS = [("QVEC_COALESCE", "2"), ("QVEC_COALESCE", "4"), ("QVEC_COALESCE", "5"), ("QVEC_COALESCE", "6"),
          ("QVEC_REG_BITS", "3"), ("QVEC_FUSE", "0"), ("QVEC_WAVE_MODE", "0"), ("QVEC_WAVE_MODE", "1"),
          ("QVEC_BLOCK_QUBITS", "10"), ("QVEC_BLOCK_QUBITS", "11"), ("QVEC_PREFETCH", "1"),
-         ("QVEC_BLOCK_KERNEL", "lds"), ("QVEC_PASS_SELECT", "greedy")]
+         ("QVEC_BLOCK_KERNEL", "lds"), ("QVEC_PASS_SELECT", "greedy"), ("QVEC_LOOKAHEAD", "8"),
+         ("QVEC_STREAM_PLAN", "1")]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -178,6 +179,28 @@ def test_scheduling_knobs_keep_the_state(qv, monkeypatch, knob, value, dtype):
         want = oracle.run(circ, n, x0=x)
         st = qv.State(n, dtype).set_basis(x).apply(circ)
         assert maxabs(host(st), want) <= TOL[dtype], (knob, value)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_streamed_planning(qv, monkeypatch, dtype):
+    """Passes launched as soon as they are planned (on by default for states
+    of 1 GiB and more; forced here), with lookahead: calls in a row with no
+    wait between them, a call planned whole in between, and a call of about
+    115 passes, whose tables outgrow the staging buffer once (the run waits
+    for the stream and reuses it from the start), against the oracle."""
+    n = 17
+    print(f"streamed planning dtype={dtype}", flush=True)
+    monkeypatch.setenv("QVEC_LOOKAHEAD", "8")
+    psi = C.random_state(n, 17)
+    st = load(qv, n, psi, dtype)
+    want = psi.copy()
+    circs = [("1", C.random_u3_layers(n, 12, 7)), ("1", C.qft(n)), ("0", C.random_mixed_circuit(n, 300, 8)),
+             ("1", C.random_u3_layers(n, 8, 9, entangler="cz")), ("1", C.random_u3_layers(n, 300, 10))]
+    for stream, circ in circs:
+        monkeypatch.setenv("QVEC_STREAM_PLAN", stream)
+        st.apply(circ)
+        want = oracle.run(circ, n, state=want)
+    assert maxabs(host(st), want) <= 10 * TOL[dtype]
 
 
 # ------------------------------------------------------------ closed forms ---

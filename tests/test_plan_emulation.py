@@ -82,3 +82,24 @@ def test_coalescing_knob_plans(emulator, kind, n, depth, seed, elem, coalesce):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "structure_errors=0" in r.stdout
 
+
+
+@pytest.mark.parametrize("park", [0, 1])
+@pytest.mark.parametrize("elem", [16, 8])
+@pytest.mark.parametrize("kind,n,depth,seed", [("cx", 20, 10, 0), ("cx", 18, 12, 1), ("cz", 19, 8, 3),
+                                               ("qft", 17, 0, 0), ("mixed", 16, 400, 5)])
+def test_lookahead_plans(emulator, kind, n, depth, seed, elem, park):
+    """Plans whose local sets are chosen with lookahead (8 extra candidates,
+    each scored with the pass after it; on by default for states of 4 GiB
+    and more) give the gate-by-gate state."""
+    if kind == "qft":
+        circ = C.qft(n)
+    elif kind == "mixed":
+        circ = C.random_mixed_circuit(n, depth, seed, ops=MIXED_OPS)
+    else:
+        circ = C.random_u3_layers(n, depth, seed, entangler=kind)
+    coalesce = 3 if elem == 16 else 4
+    r = subprocess.run([emulator, str(n), str(elem), str(park), str(coalesce), "8"], input=gate_lines(circ),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "structure_errors=0" in r.stdout
