@@ -545,6 +545,8 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     o.group_reads = !(gr && std::strcmp(gr, "0") == 0);
     const char* mf = std::getenv("QVEC_MFMA");  // "1": complex64 4x4 updates on the matrix cores
     o.mfma = o.reg_bits > 0 && elem == 8 && n_states == 1 && mf && std::strcmp(mf, "1") == 0;
+    const char* fp = std::getenv("QVEC_FOLD_PERMS");  // "0": register permutations stay in the op loop
+    o.fold_perms = !(fp && std::strcmp(fp, "0") == 0);
     const char* pk = std::getenv("QVEC_PARK");
     o.park = o.reg_bits > 0 && pk && std::strcmp(pk, "1") == 0;
     const char* wm = std::getenv("QVEC_WAVE_MODE");  // "0" | "1" | "2": see PlanOptions::wave_mode

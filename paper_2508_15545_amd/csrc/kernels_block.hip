@@ -900,6 +900,21 @@ void k_block_reg(T* __restrict__ s0, T* __restrict__ s1,
                 cur = nxt;
             }
         }
+        // Register permutations that end the stage (the n_exit ops after its
+        // n_ops; an exchange follows) move the registers' exchange offsets
+        // instead of their values: register k's offset becomes that of the
+        // index it now holds, the current one XOR a uniform term (aux) for
+        // the registers in kmask, where the block and the thread meet the
+        // op's controls.
+        const int nexit = sh.n_exit;
+        for (int e = 0; e < nexit; e++) {
+            const TileOp& x = sop[nops + e];
+            if ((base & x.gctrl) != x.gctrl) continue;  // uniform over the block
+            const uint32_t d = (cur_tl & x.tctrl) == x.tctrl ? (uint32_t)x.aux : 0u;
+            const uint32_t fm = x.kmask;
+#pragma unroll
+            for (int k = 0; k < R; k++) aoff[k] ^= ((fm >> k) & 1u) ? d : 0u;
+        }
     }
 
     // Store mapping (the last stage's, when its lanes keep the 128-byte runs

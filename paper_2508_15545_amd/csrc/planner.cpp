@@ -469,6 +469,72 @@ void set_reg_codes(PlanPass& pp, int r, bool mfma)
     }
 }
 
+// Register permutations (X on a window bit, with or without controls, and
+// CNOT within the window) that end a stage, i.e. no later op of the stage
+// touches their positions, change only which register holds which index.
+// When an exchange follows (the next stage's, or the final one before the
+// store), the kernel leaves the values where they are and instead moves the
+// registers' exchange-buffer offsets: the slot map is linear over XOR, so
+// register k's offset in the current mapping becomes that of k ^ 2^j, i.e.
+// it gains the uniform term woff[2^j] of the mapping in effect. Such ops go
+// after the stage's n_ops as its n_exit ops, each with the registers whose
+// offsets move (kmask: all for X; the pairs its register controls select for
+// controlled X; those with the control bit set for CNOT) and that term (aux);
+// the block and thread parts of their controls stay as for any op.
+void fold_trailing_perms(PlanPass& pp, int r)
+{
+    const StageHdr* eff = &pp.hdr.nat;  // mapping in effect during the stage
+    for (size_t si = 0; si < pp.stages.size(); si++) {
+        StageHdr& st = pp.stages[si];
+        if (st.wave_local != XCH_NONE) eff = &st;
+        st.n_exit = 0;
+        const bool xch_next = si + 1 < pp.stages.size() ? pp.stages[si + 1].wave_local != XCH_NONE
+                                                        : pp.hdr.final_wave_local != XCH_NONE;
+        if (!xch_next || st.n_ops == 0) continue;
+        std::vector<TileOp> keep, exits;
+        uint32_t later = 0;
+        for (int o = st.op_begin + st.n_ops - 1; o >= st.op_begin; o--) {
+            const TileOp& t = pp.ops[o];
+            uint32_t mine = ~0u;  // phases, reads and the rest: every position
+            if (t.kind == T_DENSE1 || t.kind == T_XPERM || t.kind == T_DENSE2 || t.kind == T_SWAP ||
+                t.kind == T_DIAG || t.kind == T_SIGN || (t.kind == T_GRAD && t.gen == GEN_Z)) {
+                uint32_t dense, diag;
+                op_positions(t, &dense, &diag);
+                mine = dense | diag;
+            }
+            const bool x = t.code >= RC_X && t.code < RC_X + kMaxRegBits + 1;
+            const bool xc = t.code >= RC_XC && t.code < RC_XC + kMaxRegBits + 1;
+            const bool cx = t.code >= RC_CX && t.code < RC_CX + 25;
+            if ((x || xc || cx) && !(mine & later)) {
+                TileOp e = t;
+                const int j = t.j0;  // the target's window bit
+                uint32_t fm = 0;
+                for (int k = 0; k < (1 << r); k++) {
+                    if (x) fm |= 1u << k;
+                    else if (xc) {
+                        const int k0 = k & ~(1 << j);
+                        if ((t.kmask >> k0) & 1u) fm |= 1u << k;
+                    } else if ((k >> t.j1) & 1) {
+                        fm |= 1u << k;
+                    }
+                }
+                e.kmask = fm;
+                e.aux = (int32_t)eff->woff[1u << j];
+                exits.push_back(e);
+            } else {
+                keep.push_back(t);
+            }
+            later |= mine;
+        }
+        if (exits.empty()) continue;
+        int o = st.op_begin;
+        for (auto it = keep.rbegin(); it != keep.rend(); ++it) pp.ops[o++] = *it;
+        for (auto it = exits.rbegin(); it != exits.rend(); ++it) pp.ops[o++] = *it;
+        st.n_ops = (int32_t)keep.size();
+        st.n_exit = (int32_t)exits.size();
+    }
+}
+
 // ------------------------------------------------------------ fusion ---
 // Inside one block pass, one-qubit gates are folded into neighbouring
 // two-qubit gates when that saves work: a 4x4 update of a quadruple costs
@@ -1489,6 +1555,7 @@ void plan_circuit_stream(int n, const std::vector<PlanItem>& items_in, const Pla
             if (opt.group_reads && grads > 1) group_z_reads(pp, opt.reg_bits);
             diag_to_sign(pp);
             set_reg_codes(pp, opt.reg_bits, opt.mfma && elem == 8 && opt.n_states == 1);
+            if (opt.fold_perms) fold_trailing_perms(pp, opt.reg_bits);
             set_io_offsets(pp.hdr, opt.reg_bits, moved ? store_q : nullptr);
             check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);
         }

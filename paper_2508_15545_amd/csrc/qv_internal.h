@@ -170,7 +170,10 @@ struct StageHdr {
     // positions), then the wave-index bits
     int32_t tpos[kMaxThreadBits];
     int32_t wave_local;  // exchange into this mapping: XCH_NONE / XCH_WAVE / XCH_BLOCK
-    int32_t pad;
+    // register kernel: ops after the n_ops of the stage that are register
+    // permutations applied to the registers' exchange offsets, not to their
+    // values (see fold_trailing_perms)
+    int32_t n_exit;
     // byte offset in the exchange buffer of register k's window bits
     // (lds_slot of the window part, times the slot size: 8 bytes for
     // complex64 and for the single-state complex128 kernel, which exchanges
@@ -262,6 +265,8 @@ struct PlanOptions {
     bool group_reads = true;      // Z reads waiting together share one op (register kernel)
     bool mfma = false;            // uncontrolled 4x4 updates as matrix-core ops (RC_D2M; complex64,
                                   // single state)
+    bool fold_perms = true;       // register permutations at the end of a stage into the next
+                                  // exchange's offsets (register kernel)
 };
 
 // A unit of planning: a gate, optionally preceded by a gradient read of its

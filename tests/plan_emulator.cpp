@@ -86,7 +86,9 @@ static void run_block_pass(std::vector<C>& psi, int n, const PlanPass& pp)
         // ops by stage
         for (size_t si = 0; si < pp.stages.size(); si++) {
             const StageHdr& st = pp.stages[si];
-            for (int o = st.op_begin; o < st.op_begin + st.n_ops; o++) {
+            // the stage's ops, then its exit permutations (which the kernel
+            // applies to the registers' exchange offsets) as ops at its end
+            for (int o = st.op_begin; o < st.op_begin + st.n_ops + st.n_exit; o++) {
                 const TileOp& t = pp.ops[o];
                 if ((base & t.gctrl) != t.gctrl) continue;
                 const cd* M = pp.mats.data() + t.mat;
@@ -237,11 +239,48 @@ static int check_structure(const std::vector<PlanPass>& passes)
                     return;
                 }
         };
-        for (const StageHdr& st : pp.stages)
+        for (size_t si = 0; si < pp.stages.size(); si++) {
+            const StageHdr& st = pp.stages[si];
             if (st.wave_local != XCH_NONE) {
                 check_xch(st, st.wave_local);
                 cur = &st;
             }
+            if (st.n_exit == 0) continue;
+            // exit permutations: an exchange follows, and XOR-ing the term
+            // into the offsets of the registers in kmask gives each of them
+            // the offset of its partner index in the mapping in effect
+            const bool xch_next = si + 1 < pp.stages.size() ? pp.stages[si + 1].wave_local != XCH_NONE
+                                                            : h.final_wave_local != XCH_NONE;
+            if (!xch_next) {
+                std::printf("pass %zu: stage %zu has exit permutations but no exchange after it\n", pi, si);
+                bad++;
+            }
+            for (int o = st.op_begin + st.n_ops; o < st.op_begin + st.n_ops + st.n_exit; o++) {
+                const TileOp& t = pp.ops[o];
+                const uint32_t jb = 1u << t.j0;
+                bool ok = t.kind == T_XPERM && t.j0 >= 0 && t.j0 < r && cur->w[t.j0] == t.a;
+                // kmask: the registers whose window bits meet the op's controls
+                // inside the window; tctrl: its controls on thread bits
+                const uint32_t wc = t.lctrl & cur->wmask;
+                ok = ok && t.tctrl == (t.lctrl & ~cur->wmask);
+                for (uint32_t k = 0; ok && k < (1u << r); k++) {
+                    uint32_t wl = 0;
+                    for (int j = 0; j < r; j++)
+                        if ((k >> j) & 1u) wl |= 1u << cur->w[j];
+                    ok = (((t.kmask >> k) & 1u) != 0) == ((wl & wc) == wc);
+                }
+                for (uint32_t k = 0; ok && k < (1u << r); k++) {
+                    if (!((t.kmask >> k) & 1u)) continue;
+                    ok = ((t.kmask >> (k ^ jb)) & 1u) != 0;
+                    for (uint32_t tid = 0; ok && tid < (1u << tb); tid++)
+                        ok = (offset_of(*cur, tid, k) ^ (uint32_t)t.aux) == offset_of(*cur, tid, k ^ jb);
+                }
+                if (!ok) {
+                    std::printf("pass %zu: exit permutation %d does not map the offsets of its registers\n", pi, o);
+                    bad++;
+                }
+            }
+        }
         if (h.final_wave_local != XCH_NONE) {
             check_xch(h.out, h.final_wave_local);
         } else {
@@ -312,6 +351,7 @@ int main(int argc, char** argv)
     o.prefuse = true;
     o.park = std::atoi(argv[3]) > 0;
     if (argc > 5) o.lookahead_sets = std::atoi(argv[5]);  // candidate local sets scored with the next pass
+    if (argc > 6) o.fold_perms = std::atoi(argv[6]) > 0;  // exit permutations (default on)
     const std::vector<PlanPass> passes = plan_circuit(n, items, o, elem);
     const int bad = check_structure(passes);
     std::vector<C> psi(1ull << n), ref;
@@ -334,7 +374,10 @@ int main(int argc, char** argv)
     }
     double err = 0;
     for (size_t i = 0; i < psi.size(); i++) err = std::max(err, std::abs(psi[i] - ref[i]));
-    std::printf("n=%d elem=%d passes=%zu structure_errors=%d bank_conflicts=%d maxerr=%.3e\n", n, elem,
-                passes.size(), bad, g_bank_conflicts, err);
+    int exits = 0;
+    for (const PlanPass& pp : passes)
+        for (const StageHdr& st : pp.stages) exits += st.n_exit;
+    std::printf("n=%d elem=%d passes=%zu structure_errors=%d bank_conflicts=%d exit_perms=%d maxerr=%.3e\n", n,
+                elem, passes.size(), bad, g_bank_conflicts, exits, err);
     return (bad == 0 && err < 1e-10) ? 0 : 1;
 }
