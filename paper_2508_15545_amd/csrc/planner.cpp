@@ -470,23 +470,60 @@ void set_reg_codes(PlanPass& pp, int r, bool mfma)
 }
 
 // Register permutations (X on a window bit, with or without controls, and
-// CNOT within the window) that end a stage, i.e. no later op of the stage
-// touches their positions, change only which register holds which index.
-// When an exchange follows (the next stage's, or the final one before the
-// store), the kernel leaves the values where they are and instead moves the
-// registers' exchange-buffer offsets: the slot map is linear over XOR, so
-// register k's offset in the current mapping becomes that of k ^ 2^j, i.e.
-// it gains the uniform term woff[2^j] of the mapping in effect. Such ops go
-// after the stage's n_ops as its n_exit ops, each with the registers whose
-// offsets move (kmask: all for X; the pairs its register controls select for
-// controlled X; those with the control bit set for CNOT) and that term (aux);
-// the block and thread parts of their controls stay as for any op.
-void fold_trailing_perms(PlanPass& pp, int r)
+// CNOT within the window) only change which register holds which local
+// index. When no later op of the stage touches their positions and an
+// exchange follows (the next stage's, or the final one before the store),
+// the kernel leaves the values where they are and moves the exchange-buffer
+// offsets instead: the slot map is linear over XOR, so a register now
+// holding index l ^ 2^a takes the offset of its old one XOR the uniform term
+// slot(2^a) (times the slot size), for the registers the op moves (kmask:
+// those whose window bits meet its controls inside the window) in the
+// threads and blocks that meet its other controls (tctrl, gctrl). Such ops
+// are kept after a stage's n_ops as its n_exit ops, with that term in aux.
+// Their targets are window bits, so the values stay in their thread (and
+// wave: after a within-wave exchange, other waves may still be reading the
+// slots of their own indices).
+void fold_trailing_perms(PlanPass& pp, int r, int slot_bytes)
 {
-    const StageHdr* eff = &pp.hdr.nat;  // mapping in effect during the stage
+    const int e = slot_bytes == 16 ? 4 : 5;
+    auto positions = [](const TileOp& t) {
+        uint32_t mine = ~0u;  // phases, reads and the rest: every position
+        if (t.kind == T_DENSE1 || t.kind == T_XPERM || t.kind == T_DENSE2 || t.kind == T_SWAP || t.kind == T_DIAG ||
+            t.kind == T_SIGN || (t.kind == T_GRAD && t.gen == GEN_Z)) {
+            uint32_t dense, diag;
+            op_positions(t, &dense, &diag);
+            mine = dense | diag;
+        }
+        return mine;
+    };
+    auto is_perm = [](const TileOp& t) {
+        return t.kind == T_XPERM && ((t.code >= RC_X && t.code < RC_X + kMaxRegBits + 1) ||
+                                     (t.code >= RC_XC && t.code < RC_XC + kMaxRegBits + 1) ||
+                                     (t.code >= RC_CX && t.code < RC_CX + 25));
+    };
+    // the op as an exit of a stage whose mapping is m
+    auto make_exit = [&](TileOp t, const StageHdr& m) {
+        const uint32_t wc = t.lctrl & m.wmask;
+        t.tctrl = t.lctrl & ~m.wmask;
+        uint32_t fm = 0;
+        for (int k = 0; k < (1 << r); k++) {
+            uint32_t l = 0;
+            for (int j = 0; j < r; j++)
+                if ((k >> j) & 1) l |= 1u << m.w[j];
+            if ((l & wc) == wc) fm |= 1u << k;
+        }
+        t.kmask = fm;
+        t.aux = (int32_t)(lds_slot(1u << t.a, e) * (uint32_t)slot_bytes);
+        return t;
+    };
+    std::vector<const StageHdr*> eff(pp.stages.size());  // mapping in effect during each stage
+    const StageHdr* cur = &pp.hdr.nat;
+    for (size_t si = 0; si < pp.stages.size(); si++) {
+        if (pp.stages[si].wave_local != XCH_NONE) cur = &pp.stages[si];
+        eff[si] = cur;
+    }
     for (size_t si = 0; si < pp.stages.size(); si++) {
         StageHdr& st = pp.stages[si];
-        if (st.wave_local != XCH_NONE) eff = &st;
         st.n_exit = 0;
         const bool xch_next = si + 1 < pp.stages.size() ? pp.stages[si + 1].wave_local != XCH_NONE
                                                         : pp.hdr.final_wave_local != XCH_NONE;
@@ -495,32 +532,9 @@ void fold_trailing_perms(PlanPass& pp, int r)
         uint32_t later = 0;
         for (int o = st.op_begin + st.n_ops - 1; o >= st.op_begin; o--) {
             const TileOp& t = pp.ops[o];
-            uint32_t mine = ~0u;  // phases, reads and the rest: every position
-            if (t.kind == T_DENSE1 || t.kind == T_XPERM || t.kind == T_DENSE2 || t.kind == T_SWAP ||
-                t.kind == T_DIAG || t.kind == T_SIGN || (t.kind == T_GRAD && t.gen == GEN_Z)) {
-                uint32_t dense, diag;
-                op_positions(t, &dense, &diag);
-                mine = dense | diag;
-            }
-            const bool x = t.code >= RC_X && t.code < RC_X + kMaxRegBits + 1;
-            const bool xc = t.code >= RC_XC && t.code < RC_XC + kMaxRegBits + 1;
-            const bool cx = t.code >= RC_CX && t.code < RC_CX + 25;
-            if ((x || xc || cx) && !(mine & later)) {
-                TileOp e = t;
-                const int j = t.j0;  // the target's window bit
-                uint32_t fm = 0;
-                for (int k = 0; k < (1 << r); k++) {
-                    if (x) fm |= 1u << k;
-                    else if (xc) {
-                        const int k0 = k & ~(1 << j);
-                        if ((t.kmask >> k0) & 1u) fm |= 1u << k;
-                    } else if ((k >> t.j1) & 1) {
-                        fm |= 1u << k;
-                    }
-                }
-                e.kmask = fm;
-                e.aux = (int32_t)eff->woff[1u << j];
-                exits.push_back(e);
+            const uint32_t mine = positions(t);
+            if (is_perm(t) && !(mine & later)) {
+                exits.push_back(make_exit(t, *eff[si]));
             } else {
                 keep.push_back(t);
             }
@@ -1555,7 +1569,7 @@ void plan_circuit_stream(int n, const std::vector<PlanItem>& items_in, const Pla
             if (opt.group_reads && grads > 1) group_z_reads(pp, opt.reg_bits);
             diag_to_sign(pp);
             set_reg_codes(pp, opt.reg_bits, opt.mfma && elem == 8 && opt.n_states == 1);
-            if (opt.fold_perms) fold_trailing_perms(pp, opt.reg_bits);
+            if (opt.fold_perms) fold_trailing_perms(pp, opt.reg_bits, opt.lds_elem > 0 ? opt.lds_elem : elem);
             set_io_offsets(pp.hdr, opt.reg_bits, moved ? store_q : nullptr);
             check_mappings(pp, opt.reg_bits, moved ? store_q : nullptr);
         }

@@ -182,6 +182,22 @@ static int check_structure(const std::vector<PlanPass>& passes)
             std::sort(v.begin(), v.end());
             return v;
         };
+        // the index each (thread, register) holds in the current mapping: its
+        // own, until exit permutations at a stage's end move the values
+        // (the kernel then writes it at the offset of the index it holds)
+        std::vector<uint32_t> held;
+        auto reset_held = [&](const StageHdr& m) {
+            held.assign((size_t)1 << b, 0);
+            for (uint32_t tid = 0; tid < (1u << tb); tid++)
+                for (uint32_t k = 0; k < (1u << r); k++) held[(tid << r) | k] = index_of(m, tid, k);
+        };
+        auto held_wave_set = [&](int w) {
+            std::vector<uint32_t> v;
+            for (uint32_t tid = (uint32_t)w * 64; tid < (uint32_t)(w + 1) * 64 && tid < (1u << tb); tid++)
+                for (uint32_t k = 0; k < (1u << r); k++) v.push_back(held[(tid << r) | k]);
+            std::sort(v.begin(), v.end());
+            return v;
+        };
         bool block_xch = h.final_wave_local == XCH_BLOCK;
         const StageHdr* cur = &h.nat;
         // Exchange-buffer byte offset of (thread, register) under a mapping,
@@ -233,19 +249,28 @@ static int check_structure(const std::vector<PlanPass>& passes)
             if (kind != XCH_NONE) lds_round_trip(to);
             if (kind != XCH_WAVE) return;
             for (int w = 0; w < nwaves; w++)
-                if (wave_set(*cur, w) != wave_set(to, w)) {
+                if (held_wave_set(w) != wave_set(to, w)) {
                     std::printf("pass %zu: a within-wave exchange changes wave %d's indices\n", pi, w);
                     bad++;
                     return;
                 }
         };
+        reset_held(*cur);
         for (size_t si = 0; si < pp.stages.size(); si++) {
             const StageHdr& st = pp.stages[si];
             if (st.wave_local != XCH_NONE) {
                 check_xch(st, st.wave_local);
                 cur = &st;
+                reset_held(*cur);
             }
             if (st.n_exit == 0) continue;
+            // the values move as the exits say (blocks that meet their outer
+            // controls: the within-wave check must hold for them too)
+            for (int o = st.op_begin + st.n_ops; o < st.op_begin + st.n_ops + st.n_exit; o++) {
+                const TileOp& t = pp.ops[o];
+                for (uint32_t& l : held)
+                    if ((l & t.lctrl) == t.lctrl) l ^= 1u << t.a;
+            }
             // exit permutations: an exchange follows, and XOR-ing the term
             // into the offsets of the registers in kmask gives each of them
             // the offset of its partner index in the mapping in effect
@@ -255,10 +280,20 @@ static int check_structure(const std::vector<PlanPass>& passes)
                 std::printf("pass %zu: stage %zu has exit permutations but no exchange after it\n", pi, si);
                 bad++;
             }
+            // element (thread, register) of each local index in the mapping in effect
+            std::vector<std::pair<uint32_t, uint32_t>> elem_of(1u << b);
+            for (uint32_t tid = 0; tid < (1u << tb); tid++)
+                for (uint32_t k = 0; k < (1u << r); k++) elem_of[index_of(*cur, tid, k)] = {tid, k};
             for (int o = st.op_begin + st.n_ops; o < st.op_begin + st.n_ops + st.n_exit; o++) {
                 const TileOp& t = pp.ops[o];
-                const uint32_t jb = 1u << t.j0;
-                bool ok = t.kind == T_XPERM && t.j0 >= 0 && t.j0 < r && cur->w[t.j0] == t.a;
+                bool ok = t.kind == T_XPERM && t.a >= 0 && t.a < b && !((t.lctrl >> t.a) & 1u);
+                // values stay in their wave: other waves may still be reading
+                // the slots of their own indices (within-wave exchanges)
+                for (int i = 6; i < tb; i++)
+                    if (cur->tpos[i] == t.a) {
+                        std::printf("pass %zu: exit permutation %d moves values between waves\n", pi, o);
+                        bad++;
+                    }
                 // kmask: the registers whose window bits meet the op's controls
                 // inside the window; tctrl: its controls on thread bits
                 const uint32_t wc = t.lctrl & cur->wmask;
@@ -269,11 +304,17 @@ static int check_structure(const std::vector<PlanPass>& passes)
                         if ((k >> j) & 1u) wl |= 1u << cur->w[j];
                     ok = (((t.kmask >> k) & 1u) != 0) == ((wl & wc) == wc);
                 }
-                for (uint32_t k = 0; ok && k < (1u << r); k++) {
-                    if (!((t.kmask >> k) & 1u)) continue;
-                    ok = ((t.kmask >> (k ^ jb)) & 1u) != 0;
-                    for (uint32_t tid = 0; ok && tid < (1u << tb); tid++)
-                        ok = (offset_of(*cur, tid, k) ^ (uint32_t)t.aux) == offset_of(*cur, tid, k ^ jb);
+                // every element the op moves: its offset XOR the term is the
+                // offset of the element holding its partner index
+                for (uint32_t tid = 0; ok && tid < (1u << tb); tid++) {
+                    uint32_t tl = 0;
+                    for (int i = 0; i < tb; i++) tl |= ((tid >> i) & 1u) << cur->tpos[i];
+                    if ((tl & t.tctrl) != t.tctrl) continue;
+                    for (uint32_t k = 0; ok && k < (1u << r); k++) {
+                        if (!((t.kmask >> k) & 1u)) continue;
+                        const auto pe = elem_of[index_of(*cur, tid, k) ^ (1u << t.a)];
+                        ok = (offset_of(*cur, tid, k) ^ (uint32_t)t.aux) == offset_of(*cur, pe.first, pe.second);
+                    }
                 }
                 if (!ok) {
                     std::printf("pass %zu: exit permutation %d does not map the offsets of its registers\n", pi, o);
@@ -354,6 +395,14 @@ int main(int argc, char** argv)
     if (argc > 6) o.fold_perms = std::atoi(argv[6]) > 0;  // exit permutations (default on)
     const std::vector<PlanPass> passes = plan_circuit(n, items, o, elem);
     const int bad = check_structure(passes);
+    if (argc > 7 && std::atoi(argv[7]) > 0) {  // plan structure only (sizes too large to emulate)
+        int exits = 0;
+        for (const PlanPass& pp : passes)
+            for (const StageHdr& st : pp.stages) exits += st.n_exit;
+        std::printf("n=%d elem=%d passes=%zu structure_errors=%d exit_perms=%d (structure only)\n", n, elem,
+                    passes.size(), bad, exits);
+        return bad == 0 ? 0 : 1;
+    }
     std::vector<C> psi(1ull << n), ref;
     uint64_t seed = 0x9E3779B97F4A7C15ull;
     double nn = 0;

@@ -103,3 +103,19 @@ def test_lookahead_plans(emulator, kind, n, depth, seed, elem, park):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "structure_errors=0" in r.stdout
+
+
+@pytest.mark.parametrize("elem", [16, 8])
+@pytest.mark.parametrize("lookahead", [0, 8])
+def test_benchmark_plan_structure(emulator, elem, lookahead):
+    """The 29-qubit random U3 + CNOT circuit of depth 40 as planned for the
+    benchmark (structure only: the state is too large to emulate here):
+    every exchange, exit permutation and store satisfies the kernel's rules,
+    among them that no exit permutation moves values between waves (after
+    a within-wave exchange other waves may still read those slots)."""
+    circ = C.random_u3_layers(29, 40, 0)
+    coalesce = 3 if elem == 16 else 4
+    r = subprocess.run([emulator, "29", str(elem), "0", str(coalesce), str(lookahead), "1", "1"],
+                       input=gate_lines(circ), capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "structure_errors=0" in r.stdout
