@@ -406,9 +406,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep2(T* __restrict__ psi, uint64
 // half that of a 4x4 sweep).
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_sweep_swap(T* __restrict__ psi, uint64_t npairs, int qa, int qc,
-                                                         Ins ins, uint64_t ctrl)
+                                                         Ins ins, uint64_t ctrl, int sb)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t base = xcd_block(sb) * (kThreads * P) + threadIdx.x;
     const uint64_t ba = 1ull << qa, bc = 1ull << qc;
     T x[P], y[P];
     uint64_t i0[P];
@@ -504,10 +504,23 @@ hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
     if (is_swap_matrix(g)) {
         const Ins ins = make_ins(g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]));
         const uint64_t npairs = 1ull << (n - ins.cnt);
-        with_per_thread(npairs, 2, [&](auto pc) {
+        // XCD placement as for the one-qubit sweeps, keyed on the higher
+        // qubit; where both qubits' byte bits agree mod 4 (no placement
+        // separates them), index bit 15. Measured at 29 qubits complex128:
+        // (11,20) 5.46 -> 6.09, (20,28) 5.26 -> 5.49, (27,5) 5.59 -> 6.05,
+        // (2,11) 3.63 -> 3.85 TB/s against two pairs per thread in dispatch
+        // order.
+        const int qh = g.q[0] > g.q[1] ? g.q[0] : g.q[1], ql = g.q[0] > g.q[1] ? g.q[1] : g.q[0];
+        const int eb = sizeof(T) == 16 ? 4 : 3;
+        const int bit = ((qh + eb) & 3) == ((ql + eb) & 3)
+                            ? 15
+                            : sweep_xcd_bit(qh, g.ctrl | (1ull << g.q[0]) | (1ull << g.q[1]), sizeof(T));
+        const bool split = xcd_shift(bit, 1, grid_for(npairs, kThreads)) >= 0;
+        with_per_thread(npairs, split ? 1 : 2, [&](auto pc) {
             constexpr int P = decltype(pc)::value;
-            hipLaunchKernelGGL((k_sweep_swap<T, P>), dim3(grid_for(npairs, kThreads * P)), dim3(kThreads), 0, st,
-                               psi, npairs, g.q[0], g.q[1], ins, g.ctrl);
+            const unsigned grid = grid_for(npairs, kThreads * P);
+            hipLaunchKernelGGL((k_sweep_swap<T, P>), dim3(grid), dim3(kThreads), 0, st, psi, npairs, g.q[0], g.q[1],
+                               ins, g.ctrl, split ? xcd_shift(bit, P, grid) : -1);
         });
         return hipGetLastError();
     }
@@ -545,9 +558,10 @@ hipError_t launch_sweep2(T* psi, int n, const HostGate& g, hipStream_t st)
 
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_sweep_diag(T* __restrict__ psi, uint64_t count, Ins ins,
-                                                         uint64_t ctrl, int qa, int qc, T d0, T d1, T d2v, T d3)
+                                                         uint64_t ctrl, int qa, int qc, T d0, T d1, T d2v, T d3,
+                                                         int sb)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * P) + threadIdx.x;
+    const uint64_t base = xcd_block(sb) * (kThreads * P) + threadIdx.x;
     T v[P];
     uint64_t idx[P];
 #pragma unroll
@@ -575,11 +589,18 @@ hipError_t launch_sweep_diag(T* psi, int n, const HostGate& g, hipStream_t st)
     if (lane_gate(g, n)) return launch_gate_lane<T, 2>(psi, n, g, st);
     const Ins ins = make_ins(g.ctrl);
     const uint64_t count = 1ull << (n - ins.cnt);
-    with_per_thread(count, 4, [&](auto pc) {
+    // One amplitude per thread with each XCD's workgroups on index bit 15
+    // (as for the one-qubit sweeps' near partners): CZ and CP on (11,20),
+    // (20,28), (27,5) 5.4-5.9 -> 6.4-6.6 TB/s, on (2,11) 2.75 -> 3.43 TB/s of
+    // their algorithmic bytes, against four per thread in dispatch order.
+    const int bit = 15;
+    const bool split = xcd_shift(bit, 1, grid_for(count, kThreads)) >= 0;
+    with_per_thread(count, split ? 1 : 4, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        hipLaunchKernelGGL((k_sweep_diag<T, P>), dim3(grid_for(count, kThreads * P)), dim3(kThreads), 0, st, psi,
-                           count, ins, g.ctrl, g.q[0], g.q[1], to_dev<T>(g.m[0]), to_dev<T>(g.m[1]),
-                           to_dev<T>(g.m[2]), to_dev<T>(g.m[3]));
+        const unsigned grid = grid_for(count, kThreads * P);
+        hipLaunchKernelGGL((k_sweep_diag<T, P>), dim3(grid), dim3(kThreads), 0, st, psi, count, ins, g.ctrl, g.q[0],
+                           g.q[1], to_dev<T>(g.m[0]), to_dev<T>(g.m[1]), to_dev<T>(g.m[2]), to_dev<T>(g.m[3]),
+                           split ? xcd_shift(bit, P, grid) : -1);
     });
     return hipGetLastError();
 }

@@ -595,6 +595,11 @@ def test_sweeps_with_xcd_split(qv, dtype):
     # controlled sweeps: controls below, on and above the split bit
     for a, b in [(11, 20), (20, 11), (13, 21), (13, 20), (14, 20), (3, 19), (21, 0), (17, 16)]:
         gates.append(C.gate("cx", a, b))
+    # SWAP, CZ and CP sweeps, which place the XCDs' workgroups the same way
+    for a, b in [(3, 19), (20, 11), (21, 17), (7, 12), (0, 21)]:
+        gates.append(C.gate("swap", a, b))
+        gates.append(C.gate("cz", a, b))
+        gates.append(C.gate("cp", b, a, params=(0.7 + a,)))
     want = psi.copy()
     for g in gates:
         want = oracle.apply_gate(want, n, g)
