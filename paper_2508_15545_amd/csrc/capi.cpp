@@ -568,10 +568,13 @@ PlanOptions plan_options(int n, size_t elem, int n_states)
     // Lookahead in each pass's choice of local qubits (fewer passes for more
     // host time: about 1 ms per pass with 8 candidates) on states of 4 GiB
     // and more, where a pass takes milliseconds on the GPU and
-    // sv_apply_fused plans each pass while the previous one runs.
+    // sv_apply_fused plans each pass while the previous one runs. 16
+    // candidates for complex64 (29-qubit benchmark step: 42 instead of 44
+    // passes, 125.3 against 127.1 ms), 8 for complex128 (16 found no fewer
+    // passes there and were slower).
     // QVEC_LOOKAHEAD=<k> sets the candidates (0: off).
     const uint64_t state_bytes = ((uint64_t)1 << n) * (uint64_t)elem * (uint64_t)n_states;
-    o.lookahead_sets = (n_states == 1 && state_bytes >= (4ull << 30)) ? 8 : 0;
+    o.lookahead_sets = (n_states == 1 && state_bytes >= (4ull << 30)) ? (elem == 8 ? 16 : 8) : 0;
     const char* la = std::getenv("QVEC_LOOKAHEAD");
     if (la) {
         const int v = std::atoi(la);

@@ -163,7 +163,7 @@ def test_qubit_moves_between_passes(qv, monkeypatch, kind, n, seed, dtype):
 KNOBS = [("QVEC_COALESCE", "2"), ("QVEC_COALESCE", "4"), ("QVEC_COALESCE", "5"), ("QVEC_COALESCE", "6"),
          ("QVEC_REG_BITS", "3"), ("QVEC_FUSE", "0"), ("QVEC_WAVE_MODE", "0"), ("QVEC_WAVE_MODE", "1"),
          ("QVEC_BLOCK_QUBITS", "10"), ("QVEC_BLOCK_QUBITS", "11"), ("QVEC_PREFETCH", "1"),
-         ("QVEC_BLOCK_KERNEL", "lds"), ("QVEC_PASS_SELECT", "greedy"), ("QVEC_LOOKAHEAD", "8"),
+         ("QVEC_BLOCK_KERNEL", "lds"), ("QVEC_PASS_SELECT", "greedy"), ("QVEC_LOOKAHEAD", "8"), ("QVEC_LOOKAHEAD", "16"),
          ("QVEC_STREAM_PLAN", "1"), ("QVEC_FOLD_PERMS", "0")]
 
 

@@ -106,7 +106,7 @@ def test_lookahead_plans(emulator, kind, n, depth, seed, elem, park):
 
 
 @pytest.mark.parametrize("elem", [16, 8])
-@pytest.mark.parametrize("lookahead", [0, 8])
+@pytest.mark.parametrize("lookahead", [0, 8, 16])
 def test_benchmark_plan_structure(emulator, elem, lookahead):
     """The 29-qubit random U3 + CNOT circuit of depth 40 as planned for the
     benchmark (structure only: the state is too large to emulate here):
