@@ -195,10 +195,15 @@ def test_streamed_planning(qv, monkeypatch, dtype):
     st = load(qv, n, psi, dtype)
     want = psi.copy()
     circs = [("1", C.random_u3_layers(n, 12, 7)), ("1", C.qft(n)), ("0", C.random_mixed_circuit(n, 300, 8)),
-             ("1", C.random_u3_layers(n, 8, 9, entangler="cz")), ("1", C.random_u3_layers(n, 300, 10))]
+             ("1", C.random_u3_layers(n, 8, 9, entangler="cz")), ("1", C.random_u3_layers(n, 300, 10)),
+             ("lds", C.random_mixed_circuit(n, 200, 11))]
     for stream, circ in circs:
-        monkeypatch.setenv("QVEC_STREAM_PLAN", stream)
+        # "lds": streamed passes of the LDS-resident block kernel
+        monkeypatch.setenv("QVEC_STREAM_PLAN", "1" if stream == "lds" else stream)
+        if stream == "lds":
+            monkeypatch.setenv("QVEC_BLOCK_KERNEL", "lds")
         st.apply(circ)
+        monkeypatch.delenv("QVEC_BLOCK_KERNEL", raising=False)
         want = oracle.run(circ, n, state=want)
     assert maxabs(host(st), want) <= 10 * TOL[dtype]
 
